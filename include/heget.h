@@ -1,0 +1,119 @@
+/*
+ * heget.h - C ABI of the MI355X (gfx950) tree-level QCD matrix-element library.
+ *
+ * The library evaluates, for many phase-space points at once, the squared
+ * tree-level matrix element of a massless QCD process
+ *
+ *     |M|^2 = 1/4 sum_lambda  sum_{alpha,beta} J_alpha N_alpha,beta J_beta^*
+ *
+ * averaged over the spins and colours of the two initial partons and summed
+ * over those of the final ones, as defined in section 2.1 of Hagiwara et al.,
+ * "Calculation of HELAS amplitudes for QCD processes using graphics processing
+ * unit (GPU)" (arXiv:0909.5257): eq. (matrix-element) for the diagram sum,
+ * eq. (color-amplitude) for the colour-basis amplitudes J, eq. (color-matrix)
+ * for N, eq. (color-averaged-amplitude) for the colour sum and the helicity
+ * sum-average defined right after it.  The identical-particle factor that the
+ * paper puts on the phase space (remark after eq. phase-space) is NOT applied.
+ *
+ * Supported processes are those of the paper's eq. (processes) / Table 1 for
+ * which kernels were generated at build time; heget_num_processes and
+ * heget_process_spec list them.
+ *
+ * Status codes: every entry point returns HEGET_OK or an error code and never
+ * throws.  Argument errors are detected before any device work is queued.
+ * Device errors of asynchronous work surface as HEGET_E_DEVICE from a later
+ * call or from the caller's stream synchronisation.
+ */
+#ifndef HEGET_H
+#define HEGET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct heget_process* heget_process_t;
+
+typedef enum {
+  HEGET_OK = 0,
+  HEGET_E_INVALID_ARG = 1,          /* null / misaligned pointer, bad size, bad alpha_s */
+  HEGET_E_UNSUPPORTED_PROCESS = 2,  /* spec not parsable or no kernel generated for it */
+  HEGET_E_OUT_OF_MEMORY = 3,        /* device allocation of process state failed */
+  HEGET_E_DEVICE = 4                /* HIP runtime error (launch or copy) */
+} heget_status;
+
+typedef enum {
+  HEGET_FP64 = 0,   /* every step in float64 */
+  HEGET_MIXED = 1   /* wavefunctions, currents and amplitudes in float32; momenta,
+                       invariants, JAMP accumulation and colour sum in float64 */
+} heget_precision;
+
+/* Create a process handle.
+ *   spec      process string "a b > f1 f2 ...", partons g, u, u~ separated by
+ *             blanks, e.g. "g g > g g g g", "u u~ > g g g g g", "u u > u u g g g".
+ *             Leg order of the momenta is the order written here.
+ *   precision HEGET_FP64 or HEGET_MIXED.
+ *   out       receives the handle; the library owns the process state (the
+ *             colour matrix uploaded to the current HIP device) until
+ *             heget_destroy_process.
+ * The handle is bound to the HIP device current at creation and is immutable,
+ * so concurrent heget_matrix_elements calls on different streams are safe.
+ * Errors: HEGET_E_INVALID_ARG (null spec/out or bad precision),
+ * HEGET_E_UNSUPPORTED_PROCESS, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
+heget_status heget_create_process(const char* spec, heget_precision precision, heget_process_t* out);
+
+/* Static properties of a process (Table 1 counts of the paper for the
+ * supported processes).  n_helicities counts the helicity configurations that
+ * are not structural zeros of massless-quark chirality.  Any pointer may be
+ * NULL.  Errors: HEGET_E_INVALID_ARG for a NULL handle. */
+heget_status heget_process_info(heget_process_t p, int* n_ext, int* n_diagrams, int* n_colours,
+                                int* n_helicities);
+
+/* Spin/colour averaged |M|^2 for n_events phase-space points.
+ *   momenta  DEVICE pointer, float64, layout [n_events][n_ext][4] with
+ *            components (E, px, py, pz) in GeV; initial partons carry their
+ *            physical incoming momenta and final ones their outgoing momenta;
+ *            all partons massless.  16-byte aligned.  Read only.
+ *   n_events number of points, 0 <= n_events <= 2^36; 0 queues nothing.
+ *   alpha_s  strong coupling (g_s^2 = 4 pi alpha_s), finite and > 0.
+ *   me2      DEVICE pointer, float64 [n_events], written.
+ *   stream   hipStream_t to queue the work on (NULL: the default stream).
+ * Buffers are owned by the caller and must stay valid until the queued work
+ * completes.  The call is asynchronous.
+ * Errors: HEGET_E_INVALID_ARG (detected synchronously, nothing queued),
+ * HEGET_E_DEVICE (launch failure). */
+heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int64_t n_events, double alpha_s,
+                                   double* me2, void* stream);
+
+/* Exact colour matrix N_alpha,beta of eq. (color-matrix), including the
+ * 1/(n_a n_b) colour average: N = num / den element-wise, row-major K x K, in
+ * the colour basis of eq. (color-amplitude) (single traces with leg 0 first for
+ * gluons, chains for one quark line, chain pairs sharing one summed adjoint
+ * index for two quark lines; orderings in lexicographic permutation order).
+ *   n_colours receives K (required).
+ *   num, den, values  HOST arrays of K*K entries, each may be NULL.
+ * Errors: HEGET_E_INVALID_ARG for a NULL handle or n_colours. */
+heget_status heget_color_matrix(heget_process_t p, int* n_colours, int64_t* num, int64_t* den, double* values);
+
+/* Floating-point operations the kernel performs per event, counted by the
+ * generator from the routines it emits (used for roofline figures). */
+heget_status heget_process_flops(heget_process_t p, int64_t* flops_per_event);
+
+/* Release a handle and its device state.  NULL is ignored.  The caller must
+ * make sure no queued work still uses the handle. */
+void heget_destroy_process(heget_process_t p);
+
+/* Static description of a status code. */
+const char* heget_status_string(heget_status s);
+
+/* Processes compiled into the library: their count and normalised specs
+ * (index out of range returns NULL). */
+int heget_num_processes(void);
+const char* heget_process_spec(int index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEGET_H */

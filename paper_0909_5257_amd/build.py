@@ -1,0 +1,144 @@
+"""Generate the per-process HIP kernels and build libheget.so for gfx950.
+
+    python -m paper_0909_5257_amd.build [--only TAG ...] [--jobs N] [--resource-usage]
+
+Steps: for every supported process, build the shared-current DAG and the
+exact colour matrix, emit csrc/generated/proc_<tag>.hip and a registry, then
+compile each translation unit with hipcc for gfx950 and link the shared
+library next to this file.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+GEN_DIR = os.path.join(CSRC, "generated")
+BUILD_DIR = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libheget.so")
+
+# The processes of the paper's Table 1 whose kernels are compiled in.
+PROCESSES = [
+    "g g > g g", "g g > g g g", "g g > g g g g",
+    "u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
+    "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g",
+]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # no packed FP32 instructions on this target
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+]
+
+
+def generate(specs, verbose=True):
+    from .gen.emit import Emitter
+    from .gen.model import Dag, parse
+
+    os.makedirs(GEN_DIR, exist_ok=True)
+    files, tags = [], []
+    for spec in specs:
+        t0 = time.time()
+        dag = Dag(parse(spec))
+        nmat = dag.colour_matrix()
+        src = Emitter(dag, nmat).emit()
+        path = os.path.join(GEN_DIR, f"proc_{dag.proc.tag}.hip")
+        _write_if_changed(path, src)
+        files.append(path)
+        tags.append(dag.proc.tag)
+        if verbose:
+            print(f"[gen] {spec:22s} -> {os.path.basename(path)} ({time.time() - t0:.1f}s)", flush=True)
+    reg = ['#include "heget_kernel_common.hpp"']
+    reg += [f"extern const heget_proc_desc heget_desc_{t};" for t in tags]
+    reg.append("extern const heget_proc_desc* const heget_registry[] = {")
+    reg += [f"  &heget_desc_{t}," for t in tags]
+    reg.append("};")
+    reg.append(f"extern const int heget_registry_len = {len(tags)};")
+    reg_path = os.path.join(GEN_DIR, "registry.cpp")
+    _write_if_changed(reg_path, "\n".join(reg) + "\n")
+    return files, reg_path
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path) and open(path).read() == text:
+        return
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def _digest(src, cmd):
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for path in [src] + [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hpp")] + \
+            [os.path.join(ROOT, "include", "heget.h")]:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
+def _compile(src, extra, force=False):
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
+    cmd = [HIPCC] + FLAGS + extra + lang + ["-c", src, "-o", obj]
+    stamp = obj + ".sha"
+    digest = _digest(src, cmd)
+    if not force and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == digest:
+        return obj, 0.0, ""
+    t0 = time.time()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stderr[-4000:]}")
+    with open(stamp, "w") as f:
+        f.write(digest)
+    return obj, time.time() - t0, res.stderr
+
+
+def build(specs=None, jobs=None, resource_usage=False, verbose=True, force=False):
+    specs = specs or PROCESSES
+    files, reg = generate(specs, verbose)
+    srcs = [os.path.join(CSRC, "heget.cpp"), reg] + files
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
+    jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
+    objs = []
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        futs = {ex.submit(_compile, s, extra, force): s for s in srcs}
+        for fut in cf.as_completed(futs):
+            obj, dt, log = fut.result()
+            objs.append(obj)
+            if verbose:
+                print(f"[hipcc] {os.path.basename(futs[fut]):32s} {dt:6.1f}s", flush=True)
+            if resource_usage and log:
+                print(log, flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + sorted(objs)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {res.stderr[-4000:]}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[link] {LIB}", flush=True)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", nargs="*", help="process specs to build (default: all)")
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--resource-usage", action="store_true")
+    ap.add_argument("--force", action="store_true", help="recompile even when sources are unchanged")
+    a = ap.parse_args(argv)
+    build(a.only, a.jobs, a.resource_usage, force=a.force)
+
+
+if __name__ == "__main__":
+    main()

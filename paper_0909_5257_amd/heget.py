@@ -1,0 +1,137 @@
+"""Python binding of the C ABI declared in include/heget.h (argument marshalling only).
+
+Every computation happens in the HIP library libheget.so; this module only
+passes device pointers, sizes and the current HIP stream through ctypes.  It
+raises if the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libheget.so")
+
+HEGET_OK = 0
+HEGET_FP64 = 0
+HEGET_MIXED = 1
+PRECISIONS = {"fp64": HEGET_FP64, "mixed": HEGET_MIXED}
+
+_lib = None
+
+
+class HegetError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {lib().heget_status_string(status).decode()} (status {status})")
+        self.status = status
+
+
+def lib():
+    """Load libheget.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_0909_5257_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    pi32, pi64, pdbl = ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)
+    L.heget_create_process.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(vp)]
+    L.heget_create_process.restype = i32
+    L.heget_process_info.argtypes = [vp, pi32, pi32, pi32, pi32]
+    L.heget_process_info.restype = i32
+    L.heget_matrix_elements.argtypes = [vp, vp, i64, dbl, vp, vp]
+    L.heget_matrix_elements.restype = i32
+    L.heget_color_matrix.argtypes = [vp, pi32, pi64, pi64, pdbl]
+    L.heget_color_matrix.restype = i32
+    L.heget_process_flops.argtypes = [vp, pi64]
+    L.heget_process_flops.restype = i32
+    L.heget_destroy_process.argtypes = [vp]
+    L.heget_destroy_process.restype = None
+    L.heget_status_string.argtypes = [i32]
+    L.heget_status_string.restype = ctypes.c_char_p
+    L.heget_num_processes.argtypes = []
+    L.heget_num_processes.restype = i32
+    L.heget_process_spec.argtypes = [i32]
+    L.heget_process_spec.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status != HEGET_OK:
+        raise HegetError(status, what)
+
+
+def supported_processes() -> list:
+    L = lib()
+    return [L.heget_process_spec(i).decode() for i in range(L.heget_num_processes())]
+
+
+class Process:
+    """A process handle bound to the current HIP device."""
+
+    def __init__(self, spec: str, precision: str = "fp64"):
+        self.spec = spec
+        self.precision = precision
+        h = ctypes.c_void_p()
+        _check(lib().heget_create_process(spec.encode(), PRECISIONS[precision], ctypes.byref(h)),
+               f"heget_create_process({spec!r})")
+        self._h = h
+        n = [ctypes.c_int() for _ in range(4)]
+        _check(lib().heget_process_info(h, *[ctypes.byref(x) for x in n]), "heget_process_info")
+        self.n_ext, self.n_diagrams, self.n_colours, self.n_helicities = (x.value for x in n)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.heget_destroy_process(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def flops_per_event(self) -> int:
+        f = ctypes.c_int64()
+        _check(lib().heget_process_flops(self._h, ctypes.byref(f)), "heget_process_flops")
+        return f.value
+
+    def color_matrix(self):
+        """(num, den, values) numpy arrays [K, K] of the exact colour matrix."""
+        k = ctypes.c_int()
+        _check(lib().heget_color_matrix(self._h, ctypes.byref(k), None, None, None), "heget_color_matrix")
+        kk = k.value
+        num = np.zeros(kk * kk, dtype=np.int64)
+        den = np.zeros(kk * kk, dtype=np.int64)
+        val = np.zeros(kk * kk, dtype=np.float64)
+        _check(lib().heget_color_matrix(
+            self._h, ctypes.byref(k),
+            num.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            den.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            val.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "heget_color_matrix")
+        return num.reshape(kk, kk), den.reshape(kk, kk), val.reshape(kk, kk)
+
+    def matrix_elements_ptr(self, momenta_ptr: int, n_events: int, alpha_s: float, me2_ptr: int, stream: int = 0):
+        """Raw call: device pointers as integers, stream as a hipStream_t integer."""
+        _check(lib().heget_matrix_elements(self._h, ctypes.c_void_p(momenta_ptr), n_events, alpha_s,
+                                           ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream)),
+               "heget_matrix_elements")
+
+    def matrix_elements(self, momenta, alpha_s: float, out=None, stream=None):
+        """|M|^2 for a device tensor of momenta [N, n_ext, 4] float64 (torch, on the GPU)."""
+        import torch
+        if momenta.dtype != torch.float64 or not momenta.is_cuda:
+            raise TypeError("momenta must be a float64 tensor on the GPU")
+        if momenta.dim() != 3 or momenta.shape[1:] != (self.n_ext, 4):
+            raise ValueError(f"momenta must have shape [N, {self.n_ext}, 4]")
+        momenta = momenta.contiguous()
+        n = momenta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(momenta.device)
+        self.matrix_elements_ptr(momenta.data_ptr(), n, alpha_s, out.data_ptr(), stream.cuda_stream)
+        return out

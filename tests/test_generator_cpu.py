@@ -1,0 +1,116 @@
+"""Host-side checks of the process generator and of the built C ABI (no GPU needed)."""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_0909_5257_amd.gen import colour_algebra as ca
+from paper_0909_5257_amd.gen.emit import Emitter, colour_classes, patterns
+from paper_0909_5257_amd.gen.model import Dag, parse
+
+from conftest import ROOT, golden
+
+SMALL = ["g g > g g", "g g > g g g", "u u~ > g g", "u u~ > g g g", "u u~ > g g g g",
+         "u u > u u", "u u > u u g", "u u > u u g g"]
+
+
+def _table(name):
+    rows = []
+    for line in open(golden(name)):
+        if line.strip() and not line.startswith("#"):
+            rows.append([x.strip() for x in line.split("|")])
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in _table("paper_table1.txt") if r[0] != "g g > g g g g g"],
+                         ids=lambda r: r[0])
+def test_generator_table1(row):
+    dag = Dag(parse(row[0]))
+    assert len(dag.amps) == int(row[1])
+    assert len(dag.basis) == int(row[2])
+
+
+@pytest.mark.parametrize("row", [r for r in _table("paper_table3.txt") if r[0] in SMALL], ids=lambda r: r[0])
+def test_generator_table3(row):
+    dag = Dag(parse(row[0]))
+    n = dag.colour_matrix()
+    vals = {n[i][j] for i in range(len(n)) for j in range(i, len(n))} - {Fraction(0)}
+    assert len(vals) == int(row[1])
+
+
+@pytest.mark.parametrize("spec", SMALL)
+def test_generator_colour_matrix_equals_oracle(spec):
+    """The generator's Fierz-reduced N equals the oracle's literal colour sum exactly."""
+    from oracle.colour import colour_data
+    dag = Dag(parse(spec))
+    n = dag.colour_matrix()
+    cd = colour_data(spec)
+    assert n == cd.N_frac
+
+
+@pytest.mark.parametrize("spec,n_hel", [("g g > g g", 16), ("g g > g g g g", 64), ("u u~ > g g g", 16),
+                                        ("u u~ > g g g g g", 64), ("u u > u u", 6), ("u u > u u g g", 24)])
+def test_helicity_patterns(spec, n_hel):
+    """Evaluated configurations x 2 (flip partner) = non-zero helicity configurations."""
+    dag = Dag(parse(spec))
+    assert 2 * sum(p.ncfg for p in patterns(dag)) == n_hel
+
+
+def test_every_diagram_has_a_colour_class():
+    dag = Dag(parse("g g > g g g g"))
+    amps = list(range(len(dag.amps)))
+    classes = colour_classes(dag, amps)
+    assert sum(len(m) for _, m in classes) == len(amps)
+    # every cubic tree of 6 gluons is its own class: (2*6-5)!! = 105
+    assert len(classes) == 105
+
+
+def test_fierz_reduction_basics():
+    # Tr(T^a T^a) = C_F N = 4, Tr(T^a) Tr(T^a) = 0, Tr(T^a T^b T^a T^b) = -2/3
+    assert ca._reduce(ca._canon([(0, 0)])) == 4
+    assert ca._reduce(ca._canon([(0,), (0,)])) == 0
+    assert ca._reduce(ca._canon([(0, 1, 0, 1)])) == Fraction(-2, 3)
+
+
+def test_colour_commutator_matches_structure_constants():
+    """[T^a, T^b] expansions give the two orderings with opposite signs."""
+    m = ca.comm(ca.Poly.letter(1), ca.Poly.letter(2))
+    assert m.terms == {((), (1, 2)): (1, 0), ((), (2, 1)): (-1, 0)}
+
+
+# ------------------------------------------------------------ built library
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "heget.h")).read()
+    return sorted(set(re.findall(r"\b(heget_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_header_symbols():
+    path = os.path.join(ROOT, "paper_0909_5257_amd", "libheget.so")
+    if not os.path.exists(path):
+        pytest.skip("libheget.so not built (python -m paper_0909_5257_amd.build)")
+    lib = ctypes.CDLL(path)
+    names = _header_functions()
+    assert "heget_matrix_elements" in names and "heget_create_process" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_library_registry_and_status_strings():
+    path = os.path.join(ROOT, "paper_0909_5257_amd", "libheget.so")
+    if not os.path.exists(path):
+        pytest.skip("libheget.so not built")
+    from paper_0909_5257_amd import heget
+    specs = heget.supported_processes()
+    assert "g g > g g" in specs
+    L = heget.lib()
+    assert L.heget_status_string(0) == b"ok"
+    assert L.heget_process_spec(-1) is None
+    # argument errors are reported before any device call
+    h = ctypes.c_void_p()
+    assert L.heget_create_process(None, 0, ctypes.byref(h)) == 1
+    assert L.heget_create_process(b"g g > g g", 7, ctypes.byref(h)) == 1
+    assert L.heget_matrix_elements(None, None, 0, 0.118, None, None) == 1
