@@ -92,6 +92,86 @@ def cpu_baseline(workload, inputs, samples):
     return total_events / total_time, per_event, refs
 
 
+FUSED_SPECS = ["u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
+               "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g"]
+
+
+def fused_run(steps, precision="mixed", seed=7):
+    """Eight processes of uneven sizes: one-by-one launches vs the fused batch (eager and graph)."""
+    import torch
+    from paper_0909_5257_amd.heget import Process, matrix_elements_batch
+    from phasespace import KIN_C2, generate_events
+    rng = np.random.default_rng(seed)
+    sizes = [int(2 ** rng.uniform(10, 20)) for _ in FUSED_SPECS]
+    items = []
+    for i, (spec, n) in enumerate(zip(FUSED_SPECS, sizes)):
+        nf = len(spec.split(">")[1].split())
+        x = torch.from_numpy(generate_events(n, nf, KIN_C2, seed=seed, stream=i)).to("cuda")
+        items.append((Process(spec, precision), x, torch.empty(n, dtype=torch.float64, device="cuda")))
+    total = sum(sizes)
+    log(f"[bench] fused batch: {total} events over {len(items)} processes")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return total * steps / (time.perf_counter() - t0)
+
+    seq = timed(lambda: [p.matrix_elements(x, ALPHA_S, out=o) for p, x, o in items])
+    eager = timed(lambda: matrix_elements_batch(items, ALPHA_S))
+    graph = timed(lambda: matrix_elements_batch(items, ALPHA_S, use_graph=True))
+    return {"processes": FUSED_SPECS, "events": sizes, "precision": precision,
+            "sequential_events_per_s": seq, "fused_events_per_s": eager, "fused_graph_events_per_s": graph}
+
+
+SERVING_SPECS = ["g g > g g g", "g g > g g g g", "u u~ > g g g g g", "u u > u u g g g"]
+
+
+def serving_run(n_requests, rate_hz=2000.0, seed=11):
+    """Poisson arrivals of mixed-process integrator batches through the serving loop."""
+    import torch
+    from paper_0909_5257_amd.heget import Process
+    from paper_0909_5257_amd.serving import Server, latency_summary, run_poisson
+    from phasespace import KIN_C5, generate_events
+    pool = {}
+    for i, spec in enumerate(SERVING_SPECS):
+        nf = len(spec.split(">")[1].split())
+        pool[spec] = generate_events(1 << 18, nf, KIN_C5, seed=seed, stream=i)
+    log("[bench] serving pool ready")
+
+    def workload(rng):
+        spec = SERVING_SPECS[rng.integers(len(SERVING_SPECS))]
+        n = int(2 ** rng.uniform(8, 18))
+        lo = int(rng.integers(0, (1 << 18) - n + 1))
+        return spec, pool[spec][lo:lo + n]
+
+    server = Server(SERVING_SPECS, precisions=("mixed",), hbm_budget_bytes=16 << 30, n_streams=4)
+    # warm the kernels once
+    for spec in SERVING_SPECS:
+        server.submit(spec, pool[spec][:256])
+    server.drain()
+    server.completed.clear()
+    reqs, wall = run_poisson(server, workload, rate_hz, n_requests, seed=seed)
+    served = latency_summary(reqs)
+    log(f"[bench] served {served}")
+    # the plain float64 path on the same requests, one at a time
+    procs = {s: Process(s, "fp64") for s in SERVING_SPECS}
+    t0 = time.perf_counter()
+    n_ev = 0
+    for r in reqs:
+        x = torch.from_numpy(r.momenta).to("cuda")
+        procs[r.spec].matrix_elements(x, ALPHA_S)
+        torch.cuda.synchronize()
+        n_ev += r.n
+    plain = n_ev / (time.perf_counter() - t0)
+    served.update({"rate_hz": rate_hz, "processes": SERVING_SPECS, "batch": "log-uniform [256, 262144]",
+                   "precision": "mixed", "plain_fp64_serial_events_per_s": plain})
+    return served
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +179,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="small batches, for a smoke run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48, help="0 disables the serving run")
+    ap.add_argument("--no-fused", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -158,6 +240,9 @@ def main():
                 errs[spec] = float(np.max(np.abs(out[idx] / ref - 1.0)))
             accuracy[precision] = errs
 
+    serving = serving_run(args.serving_requests) if args.serving_requests > 0 else None
+    fused = None if args.no_fused else fused_run(args.steps)
+
     head = summary["mixed"]
     line = {
         "metric": METRIC,
@@ -181,6 +266,8 @@ def main():
                  "per_process": summary["fp64"]["per_process"], "roofline": summary["fp64"]["roofline"]},
         "mixed_over_fp64": head["events_per_s"] / summary["fp64"]["events_per_s"],
         "max_rel_err_vs_oracle": accuracy,
+        "serving": serving,
+        "fused_batch": fused,
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
     }

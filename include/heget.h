@@ -96,9 +96,38 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
  * Errors: HEGET_E_INVALID_ARG for a NULL handle or n_colours. */
 heget_status heget_color_matrix(heget_process_t p, int* n_colours, int64_t* num, int64_t* den, double* values);
 
-/* Floating-point operations the kernel performs per event, counted by the
- * generator from the routines it emits (used for roofline figures). */
+/* Algorithmic floating-point operations per event: every evaluated helicity
+ * configuration's external wavefunctions, each shared current once, every
+ * diagram amplitude, the JAMP accumulation and the colour quadratic form,
+ * counted by the generator from the routines it emits (roofline numerator).
+ * Errors: HEGET_E_INVALID_ARG for a NULL argument. */
 heget_status heget_process_flops(heget_process_t p, int64_t* flops_per_event);
+
+/* One item of a fused batch: a process handle and its own device buffers,
+ * with the layouts of heget_matrix_elements. */
+typedef struct {
+  heget_process_t process;
+  const double* momenta;   /* DEVICE [n_events][n_ext][4], 16-byte aligned */
+  int64_t n_events;
+  double* me2;             /* DEVICE [n_events] */
+} heget_batch_item;
+
+/* Evaluate several processes of uneven sizes as one unit of work (the per-item
+ * quantity is that of heget_matrix_elements).  The call forks from `stream`
+ * onto a pool of library-owned HIP streams (default priority), places the
+ * items on them longest-first by their flop count (heget_process_flops x
+ * n_events) and joins back into `stream`, so small and large processes run
+ * concurrently.  With use_graph != 0 the whole fork/launch/join sequence is
+ * captured once into a hipGraph, cached by the exact item list (handles,
+ * pointers, sizes, alpha_s) and replayed on later identical calls.
+ *   items    HOST array of n_items entries; all handles on the current device.
+ *   stream   hipStream_t the batch is ordered after and before (NULL: default).
+ * Every item's buffers must stay valid until the batch completes; items must
+ * not alias each other's me2.  Asynchronous like heget_matrix_elements.
+ * Errors: HEGET_E_INVALID_ARG (any item invalid: nothing is queued),
+ * HEGET_E_DEVICE (stream/graph/launch failure). */
+heget_status heget_matrix_elements_batch(const heget_batch_item* items, int n_items, double alpha_s,
+                                         int use_graph, void* stream);
 
 /* Release a handle and its device state.  NULL is ignored.  The caller must
  * make sure no queued work still uses the handle. */

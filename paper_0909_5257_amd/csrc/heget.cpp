@@ -3,12 +3,16 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
+#include <vector>
 
 #include "heget_kernel_common.hpp"
 
@@ -63,7 +67,7 @@ heget_status heget_create_process(const char* spec, heget_precision precision, h
       return HEGET_E_OUT_OF_MEMORY;
     }
     if (hipMemcpy(p->colour_table_dev, d->colour_table, bytes, hipMemcpyHostToDevice) != hipSuccess) {
-      hipFree(p->colour_table_dev);
+      (void)hipFree(p->colour_table_dev);
       delete p;
       return HEGET_E_DEVICE;
     }
@@ -101,6 +105,157 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
   return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kBatchStreams = 4;
+constexpr size_t kGraphCacheMax = 32;
+
+struct DevicePool {
+  hipStream_t streams[kBatchStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t done[kBatchStreams] = {};
+  hipStream_t capture = nullptr;
+  bool ready = false;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
+std::mutex g_batch_mutex;
+std::map<int, DevicePool> g_pools;
+std::map<std::string, GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+
+hipError_t pool_for(int dev, DevicePool** out) {
+  DevicePool& p = g_pools[dev];
+  if (!p.ready) {
+    for (int i = 0; i < kBatchStreams; ++i) {
+      hipError_t e = hipStreamCreateWithFlags(&p.streams[i], hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+      e = hipEventCreateWithFlags(&p.done[i], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    p.ready = true;
+  }
+  *out = &p;
+  return hipSuccess;
+}
+
+double item_scale(const heget_proc_desc* d, double alpha_s) {
+  return 2.0 * 0.25 * std::pow(4.0 * M_PI * alpha_s, d->n_ext - 2);
+}
+
+// Fork from `origin`, launch the items longest-first on the pool streams, join back.
+hipError_t enqueue_batch(DevicePool* pool, const heget_batch_item* items, int n, double alpha_s,
+                         hipStream_t origin) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    return (double)items[i].process->desc->algo_flops_per_event * (double)items[i].n_events;
+  };
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  double load[kBatchStreams] = {0.0};
+  bool used[kBatchStreams] = {false};
+  hipError_t e = hipEventRecord(pool->fork, origin);
+  if (e != hipSuccess) return e;
+  for (int s = 0; s < kBatchStreams; ++s) {
+    e = hipStreamWaitEvent(pool->streams[s], pool->fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (int i : order) {
+    if (items[i].n_events == 0) continue;
+    int s = (int)(std::min_element(load, load + kBatchStreams) - load);
+    load[s] += cost(i);
+    used[s] = true;
+    const heget_process* p = items[i].process;
+    e = p->desc->launch(p->precision, items[i].momenta, items[i].n_events, items[i].me2, p->colour_table_dev,
+                        item_scale(p->desc, alpha_s), pool->streams[s]);
+    if (e != hipSuccess) return e;
+  }
+  for (int s = 0; s < kBatchStreams; ++s) {
+    e = hipEventRecord(pool->done[s], pool->streams[s]);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(origin, pool->done[s], 0);
+    if (e != hipSuccess) return e;
+  }
+  (void)used;
+  return hipSuccess;
+}
+
+std::string batch_key(const heget_batch_item* items, int n, double alpha_s, int dev) {
+  std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
+  key.append(reinterpret_cast<const char*>(&alpha_s), sizeof(alpha_s));
+  key.append(reinterpret_cast<const char*>(items), sizeof(heget_batch_item) * (size_t)n);
+  return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+heget_status heget_matrix_elements_batch(const heget_batch_item* items, int n_items, double alpha_s,
+                                         int use_graph, void* stream) {
+  if (n_items < 0 || (n_items > 0 && !items)) return HEGET_E_INVALID_ARG;
+  if (!(alpha_s > 0.0) || !std::isfinite(alpha_s)) return HEGET_E_INVALID_ARG;
+  int dev = -1;
+  if (n_items == 0) return HEGET_OK;
+  if (hipGetDevice(&dev) != hipSuccess) return HEGET_E_DEVICE;
+  for (int i = 0; i < n_items; ++i) {
+    const heget_batch_item& it = items[i];
+    if (!it.process || it.n_events < 0 || it.n_events > (int64_t(1) << 36)) return HEGET_E_INVALID_ARG;
+    if (it.process->device != dev) return HEGET_E_INVALID_ARG;
+    if (it.n_events > 0 && (!it.momenta || !it.me2)) return HEGET_E_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(it.momenta) & 15u) != 0) return HEGET_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_batch_mutex);
+  DevicePool* pool = nullptr;
+  if (pool_for(dev, &pool) != hipSuccess) return HEGET_E_DEVICE;
+  hipStream_t origin = reinterpret_cast<hipStream_t>(stream);
+  if (!use_graph) return enqueue_batch(pool, items, n_items, alpha_s, origin) == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+
+  const std::string key = batch_key(items, n_items, alpha_s, dev);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    // capture on a library stream (the caller's may be the legacy default stream)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(pool->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return HEGET_E_DEVICE;
+    hipError_t e = enqueue_batch(pool, items, n_items, alpha_s, pool->capture);
+    hipError_t e2 = hipStreamEndCapture(pool->capture, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return HEGET_E_DEVICE;
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return HEGET_E_DEVICE;
+    if (g_graphs.size() >= kGraphCacheMax) {
+      auto victim = std::min_element(g_graphs.begin(), g_graphs.end(), [](const auto& a, const auto& b) {
+        return a.second.last_use < b.second.last_use;
+      });
+      (void)hipGraphExecDestroy(victim->second.exec);
+      g_graphs.erase(victim);
+    }
+    it = g_graphs.emplace(key, GraphEntry{exec, 0}).first;
+  }
+  it->second.last_use = ++g_graph_clock;
+  // order the replay after and before the caller's stream
+  if (hipEventRecord(pool->fork, origin) != hipSuccess) return HEGET_E_DEVICE;
+  if (hipStreamWaitEvent(pool->capture, pool->fork, 0) != hipSuccess) return HEGET_E_DEVICE;
+  if (hipGraphLaunch(it->second.exec, pool->capture) != hipSuccess) return HEGET_E_DEVICE;
+  if (hipEventRecord(pool->done[0], pool->capture) != hipSuccess) return HEGET_E_DEVICE;
+  if (hipStreamWaitEvent(origin, pool->done[0], 0) != hipSuccess) return HEGET_E_DEVICE;
+  return HEGET_OK;
+}
+
 heget_status heget_color_matrix(heget_process_t p, int* n_colours, int64_t* num, int64_t* den, double* values) {
   if (!p || !n_colours) return HEGET_E_INVALID_ARG;
   const int k = p->desc->n_colours;
@@ -115,13 +270,13 @@ heget_status heget_color_matrix(heget_process_t p, int* n_colours, int64_t* num,
 
 heget_status heget_process_flops(heget_process_t p, int64_t* flops_per_event) {
   if (!p || !flops_per_event) return HEGET_E_INVALID_ARG;
-  *flops_per_event = p->desc->flops_per_event;
+  *flops_per_event = p->desc->algo_flops_per_event;
   return HEGET_OK;
 }
 
 void heget_destroy_process(heget_process_t p) {
   if (!p) return;
-  if (p->colour_table_dev) hipFree(p->colour_table_dev);
+  if (p->colour_table_dev) (void)hipFree(p->colour_table_dev);
   delete p;
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "heget_device.hpp"
+
 // Per-process descriptor emitted by the generator and registered with the library.
 struct heget_proc_desc {
   const char* spec;              // normalised process string, e.g. "g g > g g g g"
@@ -13,10 +15,11 @@ struct heget_proc_desc {
   int n_helicities;              // helicity configurations that are not structural zeros
   int n_helicities_all;          // 2^n_ext
   int colour_table_len;          // doubles in colour_table (0: the kernel holds N inline)
-  const double* colour_table;    // blocked upper-triangular N for the LDS colour sum
+  const double* colour_table;    // blocked upper-triangular W for the LDS colour sum
   const long long* colour_num;   // exact N_ab = num/den, row-major K*K, includes 1/(n_a n_b)
   const long long* colour_den;
-  long long flops_per_event;     // floating-point operations of one event, counted by the generator
+  long long flops_per_event[2];  // floating-point operations one event executes (float64, mixed), incl. recomputation
+  long long algo_flops_per_event;  // the same with every shared current counted once (roofline numerator)
   hipError_t (*launch)(int precision, const double* mom, int64_t n, double* out,
                        const double* colour_table_dev, double scale, hipStream_t stream);
 };
@@ -52,17 +55,49 @@ __device__ __forceinline__ void opaque_copy(const double (&pm)[NEXT][4], double 
     }
 }
 
-// Colour quadratic form sum_{a,b} J_a N_ab J_b^* for J held in LDS as
-// jl[a][lane] = (Re J_a, Im J_a).  N is real symmetric; the table holds
-// M_ab = N_ab (b > a), N_aa / 2 (b = a), 0 (b < a) in blocks of B rows laid
+// Opaque copies: the compiler may not assume the copy equals its source, so
+// values computed from a copy in one group of amplitudes are never merged with
+// values computed in another group.  Components known to vanish for external
+// wavefunctions (eps^0, Im eps^3) are passed through unchanged.
+__device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
+
+__device__ __forceinline__ mom4<double> fresh(const mom4<double>& p) {
+  mom4<double> q = p;
+  opaque(q.e); opaque(q.x); opaque(q.y); opaque(q.z);
+  return q;
+}
+template <class R> __device__ __forceinline__ vec4<R> fresh(const vec4<R>& v) {
+  vec4<R> w = v;
+  opaque(w.c1.re); opaque(w.c1.im); opaque(w.c2.re); opaque(w.c2.im); opaque(w.c3.re);
+  return w;
+}
+template <class R> __device__ __forceinline__ wsp<R> fresh(const wsp<R>& f) {
+  wsp<R> g = f;
+  opaque(g.s0.re); opaque(g.s0.im); opaque(g.s1.re); opaque(g.s1.im);
+  return g;
+}
+__device__ __forceinline__ mom4<double> neg(const mom4<double>& p) { return {-p.e, -p.x, -p.y, -p.z}; }
+
+// Relaxed workgroup-scope float64 add into LDS (native LDS float64 atomic on gfx950).
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Share of the colour quadratic form computed by one of W waves, for a colour
+// vector held in LDS as yl[a][0|1][lane]: the wave takes row blocks
+// blk = wave, wave + W, ...  The table holds
+// M_ab = W_ab (b > a), W_aa / 2 (b = a), 0 (b < a) in blocks of B rows laid
 // out as [K/B][K][B] so that the B row values of one column are contiguous
-// and wave-uniform (scalar loads).  Result: 2 sum_a sum_b M_ab J_a . J_b.
-template <int K, int B>
-__device__ __forceinline__ double colour_sum_lds(double2 (*jl)[64], int lane, const double* __restrict__ cmat) {
-  static_assert(K % B == 0, "colour block must divide the basis size");
+// and wave-uniform (scalar loads).  Result: 2 sum over the wave's rows of
+// sum_b M_ab (Re y_a Re y_b + Im y_a Im y_b).
+template <int K, int B, int W>
+__device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int lane, int wave,
+                                                      const double* __restrict__ cmat) {
+  static_assert(K % B == 0, "colour block must divide the colour dimension");
   double q = 0.0;
 #pragma unroll 1
-  for (int blk = 0; blk < K / B; ++blk) {
+  for (int blk = wave; blk < K / B; blk += W) {
     const int a0 = blk * B;
     const double* m = cmat + (int64_t)blk * K * B;
     double tr[B], ti[B];
@@ -73,19 +108,16 @@ __device__ __forceinline__ double colour_sum_lds(double2 (*jl)[64], int lane, co
     }
 #pragma unroll 2
     for (int b = a0; b < K; ++b) {
-      const double2 jb = jl[b][lane];
+      const double jr = yl[b][0][lane], ji = yl[b][1][lane];
 #pragma unroll
       for (int a = 0; a < B; ++a) {
         const double mab = m[b * B + a];
-        tr[a] += mab * jb.x;
-        ti[a] += mab * jb.y;
+        tr[a] += mab * jr;
+        ti[a] += mab * ji;
       }
     }
 #pragma unroll
-    for (int a = 0; a < B; ++a) {
-      const double2 ja = jl[a0 + a][lane];
-      q += ja.x * tr[a] + ja.y * ti[a];
-    }
+    for (int a = 0; a < B; ++a) q += yl[a0 + a][0][lane] * tr[a] + yl[a0 + a][1][lane] * ti[a];
   }
   return 2.0 * q;
 }

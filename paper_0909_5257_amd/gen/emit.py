@@ -1,20 +1,27 @@
 """HIP source emission for one process.
 
-Kernel shape (one event per lane, one wavefront per workgroup):
+Kernel shape:
 
-* momenta are read once per event (AoS float64 [N][n][4]);
-* helicities: only configurations with leg 0 at helicity +1 are evaluated,
+* one event per lane; momenta read once per event (AoS float64 [N][n][4]);
+* helicities: only configurations with leg 0 at helicity +1 are evaluated;
   the all-flipped ones give the same colour-summed |M_lambda|^2 for massless
   real kinematics, so the sum is doubled.  Quark lines have a chirality fixed
-  by their end helicities; configurations that break chirality along a line
-  are structural zeros and never evaluated.  Each distinct quark-chirality
-  pattern is its own straight-line block (chirality is a template constant);
-  gluon helicities run in a runtime loop;
-* per configuration: external wavefunctions, shared currents (each once),
-  diagram amplitudes summed per colour class, JAMP accumulation in float64
-  (registers for small colour bases, LDS for large ones), and the colour
-  quadratic form sum_{ab} J_a N_ab J_b^* with N read from a device table;
-* |M|^2 = (sum over configurations) * scale with scale = 2 * 1/4 * g_s^(2(n-2)).
+  by their end helicities; configurations breaking chirality along a line are
+  structural zeros and never evaluated.  Each distinct quark-chirality pattern
+  is its own straight-line block (chirality is a template constant); gluon
+  helicities run in a runtime loop;
+* per configuration: diagram amplitudes are emitted colour class by colour
+  class; the shared currents they need are built on demand inside "groups" of
+  consecutive amplitudes whose simulated register footprint stays under a
+  budget.  Each group starts from opaque copies of the external momenta and
+  wavefunctions, so a current shared by two groups is recomputed rather than
+  held live across the whole kernel (the register file, not the arithmetic,
+  is what limits these kernels);
+* class sums (float64) are added into the reduced colour vector y (see
+  reduce.py) held in registers, or, for large colour spaces, in LDS shared by
+  the four waves of a workgroup that split the groups between them;
+* the colour quadratic form y^H W y closes each configuration;
+* |M|^2 = (sum over configurations) * scale, scale = 2 * 1/4 * g_s^(2(n-2)).
 """
 from __future__ import annotations
 
@@ -22,15 +29,23 @@ import itertools
 from fractions import Fraction
 
 from .model import Dag, Process
+from .reduce import ColourSpace
 
 FLOPS = {   # real floating-point operations per call, counted from the routines
     "vvv": 166, "gggg": 134, "iov": 58,
     "jvv": 156, "jggg": 120, "jio": 64, "fvi": 74, "fvo": 74,
-    "ext": 40, "subset": 12, "class_add": 4, "jamp_add": 4,
+    "ext": 40, "psum": 4, "inv": 8, "class_add": 4, "jamp_add": 4,
 }
 
-REG_JAMP_MAX = 24     # colour bases up to this size keep J in registers
-COLOUR_BLOCK = 8      # rows of the colour quadratic form handled per pass
+REG_Y_MAX = 64          # colour spaces up to this size are handled by one wave per workgroup
+CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one non-inlined chunk function
+COOP_WAVES = 4          # waves per workgroup in the LDS (cooperative) mode
+GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
+
+SIZES = {   # 32-bit registers per value
+    "double": {"V": 16, "I": 8, "O": 8, "P": 8, "Q": 0, "inv": 2, "amp": 4, "pl": 8},
+    "float": {"V": 8, "I": 4, "O": 4, "P": 8, "Q": 4, "inv": 1, "amp": 2, "pl": 8},
+}
 
 
 def _h_of_leg(proc: Process, leg: int, lam: int) -> int:
@@ -40,12 +55,11 @@ def _h_of_leg(proc: Process, leg: int, lam: int) -> int:
 class Pattern:
     """One quark-chirality assignment and the gluon helicities that go with it."""
 
-    def __init__(self, hq: dict, free_gluons: list, fixed: dict, nodes: list, amps: list):
-        self.hq = hq                      # quark leg -> chirality
-        self.free_gluons = free_gluons    # gluon legs whose helicity the cfg bits set
-        self.fixed = fixed                # gluon leg -> fixed helicity
-        self.nodes = nodes                # active node ids
-        self.amps = amps                  # active amp indices
+    def __init__(self, hq: dict, free_gluons: list, fixed: dict, amps: list):
+        self.hq = hq
+        self.free_gluons = free_gluons
+        self.fixed = fixed
+        self.amps = amps
 
     @property
     def ncfg(self):
@@ -72,7 +86,7 @@ def _active(dag: Dag, hq: dict):
             good = hq[nd[amp.args[0]].end] == hq[root]
         if good:
             amps.append(i)
-    return ok, amps
+    return amps
 
 
 def patterns(dag: Dag) -> list:
@@ -80,8 +94,7 @@ def patterns(dag: Dag) -> list:
     quarks = [l.index for l in proc.legs if l.kind != "V"]
     gluons = [l.index for l in proc.legs if l.kind == "V"]
     fixed_leg = 0   # helicity of leg 0 is fixed to +1 (flip symmetry)
-    out = []
-    seen = set()
+    out, seen = [], set()
     for lams in itertools.product((1, -1), repeat=len(quarks)):
         lam = dict(zip(quarks, lams))
         if fixed_leg in lam and lam[fixed_leg] != 1:
@@ -91,32 +104,30 @@ def patterns(dag: Dag) -> list:
         if key in seen:
             continue
         seen.add(key)
-        ok, amps = _active(dag, hq)
+        amps = _active(dag, hq)
         if not amps:
             continue
         free = [g for g in gluons if g != fixed_leg]
         fixed = {fixed_leg: 1} if fixed_leg in gluons else {}
-        out.append(Pattern(hq, free, fixed, [i for i, v in ok.items() if v], amps))
+        out.append(Pattern(hq, free, fixed, amps))
     return out
 
 
-def colour_classes(dag: Dag, amp_ids: list):
-    """Group amplitudes whose colour vectors are proportional; keep first-seen order."""
-    classes = []          # list of (vector dict, [(amp id, factor Fraction)])
-    lookup = {}
+def colour_classes(vectors: dict, amp_ids: list):
+    """Group amplitudes whose accumulation vectors are proportional (first-seen order)."""
+    classes, lookup = [], {}
     for i in amp_ids:
-        coef = dag.amps[i].coef
-        if not coef:
+        vec = vectors[i]
+        if not vec:
             continue
-        k0 = min(coef)
-        norm = tuple(sorted((k, Fraction(v, coef[k0])) for k, v in coef.items()))
+        k0 = min(vec)
+        norm = tuple(sorted((k, v / vec[k0]) for k, v in vec.items()))
         if norm in lookup:
             ci = lookup[norm]
-            base = classes[ci][0]
-            classes[ci][1].append((i, Fraction(coef[k0], base[k0])))
+            classes[ci][1].append((i, vec[k0] / classes[ci][0][k0]))
         else:
             lookup[norm] = len(classes)
-            classes.append((dict(coef), [(i, Fraction(1))]))
+            classes.append((dict(vec), [(i, Fraction(1))]))
     return classes
 
 
@@ -128,196 +139,319 @@ def _lit(x) -> str:
     return s
 
 
+class _Group:
+    """Straight-line code of one group of amplitudes, with register simulation."""
+
+    def __init__(self, em, pat, prec, gid):
+        self.em, self.pat, self.prec, self.gid = em, pat, prec, gid
+        self.lines = []
+        self.defs = {}          # value key -> (time, size)
+        self.last = {}          # value key -> last use time
+        self.t = 0
+        self.flops = 0
+
+    def _def(self, key, size):
+        self.defs[key] = (self.t, size)
+        self.last[key] = self.t
+        self.t += 1
+
+    def _use(self, key):
+        self.last[key] = self.t
+
+    def peak(self):
+        ev = [0] * (self.t + 2)
+        for key, (t0, size) in self.defs.items():
+            t1 = self.last[key]
+            if t1 > t0 and size:
+                ev[t0] += size
+                ev[t1] -= size
+        run = peak = 0
+        for x in ev:
+            run += x
+            peak = max(peak, run)
+        return peak
+
+    def name(self, key):
+        return f"g{self.gid}_{key[0]}{'_'.join(str(x) for x in key[1:])}"
+
+    def leg_mom(self, leg):
+        key = ("pl", leg)
+        if key not in self.defs:
+            self.lines.append(f"  const mom4<double> {self.name(key)} = fresh(pl{leg});")
+            self._def(key, SIZES[self.prec]["pl"])
+        self._use(key)
+        return self.name(key)
+
+    def psum(self, mask):
+        key = ("P", mask)
+        if key not in self.defs:
+            proc = self.em.proc
+            bits = [i for i in range(proc.n) if mask >> i & 1]
+            if len(bits) == 1:
+                i = bits[0]
+                src = self.leg_mom(i)
+                expr = src if proc.legs[i].eta > 0 else f"neg({src})"
+            else:
+                lo = 1 << bits[0]
+                a, b = self.psum(lo), self.psum(mask ^ lo)
+                expr = f"add({a}, {b})"
+                self.flops += FLOPS["psum"]
+            self.lines.append(f"  const mom4<double> {self.name(key)} = {expr};")
+            self._def(key, SIZES[self.prec]["P"])
+        self._use(key)
+        return self.name(key)
+
+    def qmom(self, mask):
+        key = ("Q", mask)
+        if key not in self.defs:
+            p = self.psum(mask)
+            self.lines.append(f"  const mom4<R> {self.name(key)} = to<R>({p});")
+            self._def(key, SIZES[self.prec]["Q"])
+        self._use(key)
+        return self.name(key)
+
+    def inv(self, mask):
+        key = ("I", mask)
+        if key not in self.defs:
+            p = self.psum(mask)
+            self.lines.append(f"  const R {self.name(key)} = R(1.0 / msq({p}));")
+            self._def(key, SIZES[self.prec]["inv"])
+            self.flops += FLOPS["inv"]
+        self._use(key)
+        return self.name(key)
+
+    def node(self, i):
+        key = ("c", i)
+        if key in self.defs:
+            self._use(key)
+            return self.name(key)
+        em = self.em
+        nd = em.dag.nodes[i]
+        h = self.pat.hq
+        args = [self.node(a) for a in nd.args]
+        op = nd.op
+        if op == "ext":
+            leg = em.proc.legs[nd.leg]
+            typ = "vec4<R>" if leg.kind == "V" else "wsp<R>"
+            expr = f"fresh(w{leg.index})"
+        elif op == "jvv":
+            x, y = nd.args
+            typ = "vec4<R>"
+            expr = (f"jvvxx0<R>({args[0]}, {self.qmom(em.dag.nodes[x].mask)}, {args[1]}, "
+                    f"{self.qmom(em.dag.nodes[y].mask)}, {self.inv(nd.mask)})")
+        elif op == "jggg":
+            typ = "vec4<R>"
+            expr = f"jgggx0<R>({args[0]}, {args[1]}, {args[2]}, {self.inv(nd.mask)})"
+        elif op == "jio":
+            typ = "vec4<R>"
+            expr = f"jioxx0<R, {h[em.dag.nodes[nd.args[0]].end]}>({args[0]}, {args[1]}, {self.inv(nd.mask)})"
+        elif op == "fvi":
+            typ = "wsp<R>"
+            expr = f"fvixx0<R, {h[nd.end]}>({args[0]}, {args[1]}, {self.qmom(nd.mask)}, {self.inv(nd.mask)})"
+        elif op == "fvo":
+            typ = "wsp<R>"
+            expr = f"fvoxx0<R, {h[nd.end]}>({args[0]}, {args[1]}, {self.qmom(nd.mask)}, {self.inv(nd.mask)})"
+        else:
+            raise AssertionError(op)
+        self.flops += FLOPS.get(op, 0)
+        self.lines.append(f"  const {typ} {self.name(key)} = {expr};")
+        self._def(key, SIZES[self.prec][nd.kind])
+        for a in nd.args:
+            self._use(("c", a))
+        self._use(key)
+        return self.name(key)
+
+    def amplitude(self, ai, acc, fac):
+        em = self.em
+        amp = em.dag.amps[ai]
+        root = em.proc.root
+        nd = em.dag.nodes
+        args = [self.node(a) for a in amp.args]
+        r = self.node(em.dag.ext[root])
+        if amp.op == "vvv":
+            x, y = amp.args
+            expr = (f"vvvxxx<R>({args[0]}, {self.qmom(nd[x].mask)}, {args[1]}, {self.qmom(nd[y].mask)}, "
+                    f"{r}, {self.qmom(1 << root)})")
+        elif amp.op == "gggg":
+            a, b, c = args
+            order = [(a, b, c, r), (a, c, r, b), (a, r, b, c)][amp.piece]
+            expr = "ggggxx<R>(" + ", ".join(order) + ")"
+        else:
+            expr = f"iovxx0<R, {self.pat.hq[nd[amp.args[0]].end]}>({args[0]}, {r}, {args[1]})"
+        self.flops += FLOPS[amp.op] + FLOPS["class_add"]
+        key = ("a", ai)
+        self.lines.append(f"  const cx<R> {self.name(key)} = {expr};")
+        self._def(key, SIZES[self.prec]["amp"])
+        for a in amp.args:
+            self._use(("c", a))
+        self._use(("c", em.dag.ext[root]))
+        an = self.name(key)
+        if fac == 1:
+            self.lines.append(f"  {acc}.re += double({an}.re); {acc}.im += double({an}.im);")
+        elif fac == -1:
+            self.lines.append(f"  {acc}.re -= double({an}.re); {acc}.im -= double({an}.im);")
+        else:
+            self.lines.append(f"  {acc}.re += {_lit(fac)} * double({an}.re); "
+                              f"{acc}.im += {_lit(fac)} * double({an}.im);")
+        self._use(key)
+
+
 class Emitter:
     def __init__(self, dag: Dag, nmat):
         self.dag = dag
         self.proc = dag.proc
         self.nmat = nmat
         self.k = len(dag.basis)
+        self.cs = ColourSpace(dag, nmat)
+        self.kdim = self.cs.dim
+        self.vectors = {i: self.cs.vector(a.coef) for i, a in enumerate(dag.amps)}
         self.pats = patterns(dag)
-        self.reg_jamp = self.k <= REG_JAMP_MAX
-        self.flops_per_event = 0
+        self.coop = self.kdim > REG_Y_MAX
+        self.cblock = next(b for b in (8, 6, 4, 3, 2, 1) if self.kdim % b == 0)
+        self.flops = {"double": 0, "float": 0}
+        self.algo_flops = 0
+        self.stats = {}
 
-    # ------------------------------------------------------------ helpers
-    def _mask_name(self, m):
-        return f"{m:x}"
-
-    def emit_pattern(self, pi: int, pat: Pattern) -> str:
-        dag, proc = self.dag, self.proc
-        nd = dag.nodes
-        out = []
-        w = out.append
-        done_p, done_q, done_i = set(), set(), set()
-        flops = 0
-
-        def need_p(m):
-            nonlocal flops
-            if m in done_p:
-                return f"P{self._mask_name(m)}"
-            bits = [i for i in range(proc.n) if m >> i & 1]
-            if len(bits) == 1:
-                i = bits[0]
-                eta = proc.legs[i].eta
-                sgn = "" if eta > 0 else "-"
-                w(f"  const mom4<double> P{self._mask_name(m)}{{{sgn}pm[{i}][0], {sgn}pm[{i}][1], "
-                  f"{sgn}pm[{i}][2], {sgn}pm[{i}][3]}};")
+    # ------------------------------------------------------------------ groups
+    def _plan(self, pat: Pattern, prec: str):
+        """Split the pattern's classes into register-bounded groups of amplitudes."""
+        classes = colour_classes(self.vectors, pat.amps)
+        items = [(ci, ai, fac) for ci, (_, members) in enumerate(classes) for ai, fac in members]
+        groups, cur = [], []
+        budget = GROUP_BUDGET[prec]
+        g = _Group(self, pat, prec, 0)
+        for it in items:
+            g.amplitude(it[1], "acc", it[2])
+            if cur and g.peak() > budget:
+                groups.append(cur)
+                cur = [it]
+                g = _Group(self, pat, prec, 0)
+                g.amplitude(it[1], "acc", it[2])
             else:
-                lo = 1 << bits[0]
-                a, b = need_p(lo), need_p(m ^ lo)
-                w(f"  const mom4<double> P{self._mask_name(m)} = add({a}, {b});")
-                flops += 4
-            done_p.add(m)
-            return f"P{self._mask_name(m)}"
+                cur.append(it)
+        if cur:
+            groups.append(cur)
+        return classes, groups
 
-        def need_q(m):
-            name = f"Q{self._mask_name(m)}"
-            if m not in done_q:
-                p = need_p(m)
-                w(f"  const mom4<R> {name} = to<R>({p});")
-                done_q.add(m)
-            return name
+    def _build(self, pat, prec, items, gid):
+        g = _Group(self, pat, prec, gid)
+        for ci, ai, fac in items:
+            g.amplitude(ai, f"k{ci}", fac)
+        return g
 
-        def need_is(m):
-            nonlocal flops
-            name = f"I{self._mask_name(m)}"
-            if m not in done_i:
-                p = need_p(m)
-                w(f"  const R {name} = R(1.0 / msq({p}));")
-                done_i.add(m)
-                flops += 8
-            return name
-
-        emitted = set()
+    # ------------------------------------------------------------------ code
+    def emit_pattern(self, pi: int, pat: Pattern, prec: str):
+        """Chunk functions of one pattern: list of (name, source, wave, flops)."""
+        proc = self.proc
+        classes, groups = self._plan(pat, prec)
+        last_group = {}
+        for gi, items in enumerate(groups):
+            for ci, _, _ in items:
+                last_group[ci] = gi
+        built = [self._build(pat, prec, items, gi) for gi, items in enumerate(groups)]
+        # chunks: consecutive groups, cut only where no colour class is open
+        chunks, cur, cur_flops = [], [], 0
+        for gi, b in enumerate(built):
+            cur.append(gi)
+            cur_flops += b.flops
+            open_cls = any(last_group[c] > gi for c, _, _ in groups[gi])
+            if cur_flops >= CHUNK_FLOPS and not open_cls:
+                chunks.append(cur)
+                cur, cur_flops = [], 0
+        if cur:
+            chunks.append(cur)
         h = pat.hq
-
-        def var(i):
-            return f"c{i}"
-
-        def emit_node(i):
-            nonlocal flops
-            if i in emitted:
-                return
-            node = nd[i]
-            for a in node.args:
-                emit_node(a)
-            op = node.op
-            if op == "ext":
-                leg = proc.legs[node.leg]
-                pl = f"pl{leg.index}"
-                if leg.kind == "V":
-                    if leg.index in pat.fixed:
-                        lam = str(pat.fixed[leg.index])
-                    else:
-                        bit = pat.free_gluons.index(leg.index)
-                        lam = f"((cfg >> {bit}) & 1 ? 1 : -1)"
-                    w(f"  const vec4<R> {var(i)} = vxxxx0<R>({pl}, {lam}, {'false' if leg.incoming else 'true'});")
-                elif leg.kind == "I":
-                    w(f"  const wsp<R> {var(i)} = ixxxx0<R, {h[leg.index]}>({pl});")
-                else:
-                    w(f"  const wsp<R> {var(i)} = oxxxx0<R, {h[leg.index]}>({pl});")
-                flops += FLOPS["ext"]
-            elif op == "jvv":
-                x, y = node.args
-                w(f"  const vec4<R> {var(i)} = jvvxx0<R>({var(x)}, {need_q(nd[x].mask)}, {var(y)}, "
-                  f"{need_q(nd[y].mask)}, {need_is(node.mask)});")
-                flops += FLOPS["jvv"]
-            elif op == "jggg":
-                x, y, z = node.args
-                w(f"  const vec4<R> {var(i)} = jgggx0<R>({var(x)}, {var(y)}, {var(z)}, {need_is(node.mask)});")
-                flops += FLOPS["jggg"]
-            elif op == "jio":
-                f, g = node.args
-                w(f"  const vec4<R> {var(i)} = jioxx0<R, {h[nd[f].end]}>({var(f)}, {var(g)}, {need_is(node.mask)});")
-                flops += FLOPS["jio"]
-            elif op == "fvi":
-                f, v = node.args
-                w(f"  const wsp<R> {var(i)} = fvixx0<R, {h[node.end]}>({var(f)}, {var(v)}, "
-                  f"{need_q(node.mask)}, {need_is(node.mask)});")
-                flops += FLOPS["fvi"]
-            elif op == "fvo":
-                g, v = node.args
-                w(f"  const wsp<R> {var(i)} = fvoxx0<R, {h[node.end]}>({var(g)}, {var(v)}, "
-                  f"{need_q(node.mask)}, {need_is(node.mask)});")
-                flops += FLOPS["fvo"]
-            else:
-                raise AssertionError(op)
-            emitted.add(i)
-
-        root = proc.root
-        w(f"  // quark chiralities: {', '.join(f'leg {q}: {v:+d}' for q, v in sorted(h.items())) or 'none'}")
+        prologue = []
+        w = prologue.append
         for leg in proc.legs:
-            w(f"  const mom4<double> pl{leg.index}{{pm[{leg.index}][0], pm[{leg.index}][1], "
-              f"pm[{leg.index}][2], pm[{leg.index}][3]}};")
-        if self.reg_jamp:
-            w(f"  double jr[{self.k}], ji[{self.k}];")
-            w(f"#pragma unroll")
-            w(f"  for (int a = 0; a < {self.k}; ++a) {{ jr[a] = 0.0; ji[a] = 0.0; }}")
-        else:
-            w(f"#pragma unroll 8")
-            w(f"  for (int a = 0; a < {self.k}; ++a) jl[a][lane] = make_double2(0.0, 0.0);")
+            w(f"  const mom4<double> pl{leg.index}{{pml[{leg.index}][0][lane], pml[{leg.index}][1][lane], "
+              f"pml[{leg.index}][2][lane], pml[{leg.index}][3][lane]}};")
+        for leg in proc.legs:
+            if leg.kind == "V":
+                if leg.index in pat.fixed:
+                    lam = str(pat.fixed[leg.index])
+                else:
+                    lam = f"((cfg >> {pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
+                w(f"  const vec4<R> w{leg.index} = vxxxx0<R>(pl{leg.index}, {lam}, "
+                  f"{'false' if leg.incoming else 'true'});")
+            elif leg.kind == "I":
+                w(f"  const wsp<R> w{leg.index} = ixxxx0<R, {h[leg.index]}>(pl{leg.index});")
+            else:
+                w(f"  const wsp<R> w{leg.index} = oxxxx0<R, {h[leg.index]}>(pl{leg.index});")
+        out = []
+        total_flops = 0
+        for ki, gis in enumerate(chunks):
+            lines = list(prologue)
+            w = lines.append
+            flops = FLOPS["ext"] * proc.n
+            for gi in gis:
+                items = groups[gi]
+                for ci in sorted({c for c, _, _ in items if min(g for g in range(len(groups))
+                                                                 if any(x == c for x, _, _ in groups[g])) == gi}):
+                    w(f"  cx<double> k{ci}{{0.0, 0.0}};")
+                w("  __builtin_amdgcn_sched_barrier(0);")
+                lines.extend(built[gi].lines)
+                flops += built[gi].flops
+                for ci in sorted({c for c, _, _ in items if last_group[c] == gi}):
+                    for a, sc in sorted(classes[ci][0].items()):
+                        flops += FLOPS["jamp_add"]
+                        if self.coop:
+                            w(f"  lds_add(&yl[{a}][0][lane], {_lit(sc)} * k{ci}.re); "
+                              f"lds_add(&yl[{a}][1][lane], {_lit(sc)} * k{ci}.im);")
+                        else:
+                            w(f"  yl[{a}][0][lane] += {_lit(sc)} * k{ci}.re; yl[{a}][1][lane] += {_lit(sc)} * k{ci}.im;")
+            name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_c{ki}"
+            src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+                   + "\n".join(lines) + "\n}\n")
+            out.append([name, src, 0, flops])
+            total_flops += flops
+        nwave = COOP_WAVES if self.coop else 1
+        if nwave > 1:
+            acc, wv = 0, 0
+            for c in out:
+                if wv < nwave - 1 and acc >= (wv + 1) * total_flops / nwave:
+                    wv += 1
+                c[2] = wv
+                acc += c[3]
+        cflops = total_flops + 2 * self.kdim * (self.kdim + 1)
+        self.flops[prec] += cflops * pat.ncfg
+        if prec == "double":
+            self.algo_flops += self._algorithmic_flops(pat, classes) * pat.ncfg
+        self.stats.setdefault(prec, []).append(
+            {"pattern": pi, "amps": len(pat.amps), "groups": len(groups), "chunks": len(chunks),
+             "node_evals": sum(sum(1 for k in b.defs if k[0] == "c") for b in built),
+             "max_peak": max(b.peak() for b in built),
+             "wave_flops": [sum(c[3] for c in out if c[2] == v) for v in range(nwave)]})
+        return out
 
-        emit_node(dag.ext[root])
-        for cls_i, (vec, members) in enumerate(colour_classes(dag, pat.amps)):
-            kk = f"k{cls_i}"
-            w(f"  // colour class {cls_i}")
-            w(f"  cx<double> {kk}{{0.0, 0.0}};")
-            for ai, fac in members:
-                amp = dag.amps[ai]
-                for a in amp.args:
-                    emit_node(a)
-                if amp.op == "vvv":
-                    x, y = amp.args
-                    expr = (f"vvvxxx<R>({var(x)}, {need_q(nd[x].mask)}, {var(y)}, {need_q(nd[y].mask)}, "
-                            f"{var(dag.ext[root])}, {need_q(1 << root)})")
-                elif amp.op == "gggg":
-                    x, y, z = amp.args
-                    r = var(dag.ext[root])
-                    order = [(x, y, z, r), (x, z, r, y), (x, r, y, z)][amp.piece]
-                    expr = "ggggxx<R>(" + ", ".join(o if isinstance(o, str) else var(o) for o in order) + ")"
-                else:
-                    f, v = amp.args
-                    expr = f"iovxx0<R, {h[nd[f].end]}>({var(f)}, {var(dag.ext[root])}, {var(v)})"
-                flops += FLOPS[amp.op] + FLOPS["class_add"]
-                w(f"  const cx<R> a{ai} = {expr};")
-                if fac == 1:
-                    w(f"  {kk}.re += double(a{ai}.re); {kk}.im += double(a{ai}.im);")
-                elif fac == -1:
-                    w(f"  {kk}.re -= double(a{ai}.re); {kk}.im -= double(a{ai}.im);")
-                else:
-                    w(f"  {kk}.re += {_lit(fac)} * double(a{ai}.re); {kk}.im += {_lit(fac)} * double(a{ai}.im);")
-            for a, s in sorted(vec.items()):
-                flops += FLOPS["jamp_add"]
-                if self.reg_jamp:
-                    w(f"  jr[{a}] += {_lit(s)} * {kk}.re; ji[{a}] += {_lit(s)} * {kk}.im;")
-                else:
-                    w(f"  {{ double2 t = jl[{a}][lane]; t.x += {_lit(s)} * {kk}.re; t.y += {_lit(s)} * {kk}.im; "
-                      f"jl[{a}][lane] = t; }}")
-        # colour sum
-        if self.reg_jamp:
-            w("  double q = 0.0;")
-            for a in range(self.k):
-                terms_r, terms_i = [], []
-                for b in range(a, self.k):
-                    v = self.nmat[a][b] * (Fraction(1, 2) if a == b else 1)
-                    if v == 0:
-                        continue
-                    terms_r.append(f"{_lit(v)} * jr[{b}]")
-                    terms_i.append(f"{_lit(v)} * ji[{b}]")
-                if terms_r:
-                    w(f"  q += jr[{a}] * ({' + '.join(terms_r)}) + ji[{a}] * ({' + '.join(terms_i)});")
-            w("  return 2.0 * q;")
-        else:
-            w(f"  return colour_sum_lds<{self.k}, {COLOUR_BLOCK}>(jl, lane, cmat);")
-        flops += 2 * self.k * (self.k + 1)
-        self.flops_per_event += flops * pat.ncfg
-        body = "\n".join(out)
-        jarg = "" if self.reg_jamp else ", double2 (*jl)[64], int lane, const double* __restrict__ cmat"
-        return (f"template <class R>\n__device__ __forceinline__ double pattern{pi}("
-                f"const double (&pm)[NEXT][4], int cfg{jarg}) {{\n{body}\n}}\n")
+    def _algorithmic_flops(self, pat, classes) -> int:
+        """Arithmetic of one configuration with every shared current built once."""
+        nd = self.dag.nodes
+        used, masks = set(), set()
+
+        def visit(i):
+            if i in used:
+                return
+            used.add(i)
+            for a in nd[i].args:
+                visit(a)
+        for ai in pat.amps:
+            for a in self.dag.amps[ai].args:
+                visit(a)
+        f = FLOPS["ext"] * self.proc.n
+        for i in used:
+            if nd[i].op != "ext":
+                f += FLOPS[nd[i].op]
+                masks.add(nd[i].mask)
+        f += len(masks) * (FLOPS["psum"] + FLOPS["inv"])
+        f += sum(FLOPS[self.dag.amps[ai].op] + FLOPS["class_add"] for ai in pat.amps)
+        f += sum(len(vec) * FLOPS["jamp_add"] for vec, _ in classes)
+        f += 2 * self.kdim * (self.kdim + 1)
+        return f
 
     def colour_table(self):
-        """Blocked upper-triangular colour matrix for colour_sum_lds: [K/B][K][B]."""
-        k, bsz = self.k, COLOUR_BLOCK
+        """Blocked upper-triangular W for the LDS colour sum: [K/B][K][B]."""
+        k, bsz = self.kdim, self.cblock
         out = []
         for blk in range(k // bsz):
             for b in range(k):
@@ -326,84 +460,124 @@ class Emitter:
                     if b < row:
                         v = Fraction(0)
                     elif b == row:
-                        v = self.nmat[row][b] / 2
+                        v = self.cs.w[row][b] / 2
                     else:
-                        v = self.nmat[row][b]
+                        v = self.cs.w[row][b]
                     out.append(float(v))
+        return out
+
+    def _kernel(self, prec: str, chunks_per_pattern) -> list:
+        sfx = "f64" if prec == "double" else "f32"
+        args = ("const double* __restrict__ mom, int64_t nev, double* __restrict__ out, "
+                "const double* __restrict__ cmat, double scale")
+        nwave = COOP_WAVES if self.coop else 1
+        nt = 64 * nwave
+        out = []
+        w = out.append
+        w(f"__global__ __launch_bounds__({nt}) void me2_{sfx}({args}) {{")
+        w("  const int lane = threadIdx.x & 63;")
+        w("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
+        w("  const int64_t ev = (int64_t)blockIdx.x * 64 + lane;")
+        w("  const int64_t evc = ev < nev ? ev : nev - 1;")
+        w("  if (wave == 0) {")
+        w("    double pm[NEXT][4];")
+        w("    load_momenta<NEXT>(mom, evc, pm);")
+        w("#pragma unroll")
+        w("    for (int i = 0; i < NEXT; ++i)")
+        w("#pragma unroll")
+        w("      for (int j = 0; j < 4; ++j) pml[i][j][lane] = pm[i][j];")
+        w("  }")
+        w("  double q = 0.0;")
+        for pi, (pat, chunks) in enumerate(zip(self.pats, chunks_per_pattern)):
+            w("#pragma unroll 1")
+            w(f"  for (int cfg = 0; cfg < {pat.ncfg}; ++cfg) {{")
+            w(f"    for (int a = threadIdx.x; a < {self.kdim * 128}; a += {nt}) (&yl[0][0][0])[a] = 0.0;")
+            w("    __syncthreads();")
+            for v in range(nwave):
+                names = [c[0] for c in chunks if c[2] == v]
+                if not names:
+                    continue
+                if nwave > 1:
+                    w(f"    if (wave == {v}) {{")
+                for nm in names:
+                    w(f"      {nm}(cfg, lane);")
+                if nwave > 1:
+                    w("    }")
+            w("    __syncthreads();")
+            w(f"    q += colour_sum_lds_part<{self.kdim}, {self.cblock}, {nwave}>(yl, lane, wave, cmat);")
+            w("    __syncthreads();")
+            w("  }")
+        if nwave > 1:
+            w(f"  __shared__ double qsum[{nwave}][64];")
+            w("  qsum[wave][lane] = q;")
+            w("  __syncthreads();")
+            w("  if (wave == 0) {")
+            w("    double t = 0.0;")
+            w(f"    for (int v = 0; v < {nwave}; ++v) t += qsum[v][lane];")
+            w("    if (ev < nev) out[ev] = t * scale;")
+            w("  }")
+        else:
+            w("  if (ev < nev) out[ev] = q * scale;")
+        w("}")
         return out
 
     def emit(self) -> str:
         proc, dag = self.proc, self.dag
         ns = f"p_{proc.tag}"
-        pats = [self.emit_pattern(i, p) for i, p in enumerate(self.pats)]
-        kern_args = "const double* __restrict__ mom, int64_t nev, double* __restrict__ out, " \
-                    "const double* __restrict__ cmat, double scale"
+        chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
+                  for prec in ("double", "float")}
+        nwave = COOP_WAVES if self.coop else 1
         lines = []
         w = lines.append
         w(f"// Generated by paper_0909_5257_amd.gen for the process \"{proc.spec}\".  Do not edit.")
         w(f"// diagrams {len(dag.amps)}, shared currents {len(dag.nodes) - proc.n}, colour basis {self.k}, "
-          f"helicity patterns {len(self.pats)}, evaluated configurations {sum(p.ncfg for p in self.pats)}")
+          f"reduced colour space {self.kdim}, helicity patterns {len(self.pats)}, "
+          f"evaluated configurations {sum(p.ncfg for p in self.pats)}, waves per workgroup {nwave}")
+        for prec, st in self.stats.items():
+            for s in st:
+                w(f"// {prec} pattern {s['pattern']}: {s['amps']} amplitudes in {s['groups']} groups and "
+                  f"{s['chunks']} chunks, {s['node_evals']} current evaluations, peak {s['max_peak']} "
+                  f"registers (simulated), flops per wave {s['wave_flops']}")
         w('#include "heget_device.hpp"')
         w('#include "heget_kernel_common.hpp"')
         w("")
         w("namespace heget {")
         w(f"namespace {ns} {{")
         w(f"constexpr int NEXT = {proc.n};")
-        w(f"constexpr int NCOL = {self.k};")
+        w(f"__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events")
+        w(f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event")
         w("")
-        for p in pats:
-            w(p)
-        w("template <class R>")
-        w(f"__global__ __launch_bounds__(64) void me2_kernel({kern_args}) {{")
-        w("  const int lane = threadIdx.x;")
-        w("  const int64_t ev = (int64_t)blockIdx.x * 64 + lane;")
-        w("  const int64_t evc = ev < nev ? ev : nev - 1;")
-        w("  double pm[NEXT][4];")
-        w("  load_momenta<NEXT>(mom, evc, pm);")
-        if not self.reg_jamp:
-            w("  __shared__ double2 jl[NCOL][64];")
-        w("  double q = 0.0;")
-        for i, p in enumerate(self.pats):
-            w("#pragma unroll 1")
-            w(f"  for (int cfg = 0; cfg < {p.ncfg}; ++cfg) {{")
-            w("    double pp[NEXT][4];")
-            w("    opaque_copy<NEXT>(pm, pp);")
-            call = f"pattern{i}<R>(pp, cfg)" if self.reg_jamp else f"pattern{i}<R>(pp, cfg, jl, lane, cmat)"
-            w(f"    q += {call};")
-            w("  }")
-        w("  if (ev < nev) out[ev] = q * scale;")
-        w("}")
-        w(f"template __global__ void me2_kernel<double>({kern_args});")
-        w(f"template __global__ void me2_kernel<float>({kern_args});")
+        for prec in ("double", "float"):
+            for pat_chunks in chunks[prec]:
+                for c in pat_chunks:
+                    lines.append(c[1])
+        lines.extend(self._kernel("double", chunks["double"]))
+        lines.extend(self._kernel("float", chunks["float"]))
         w("")
         w(f"}}  // namespace {ns}")
         w("}  // namespace heget")
         w("")
-        # host side launcher and descriptor (host compilation pass only)
         w("#if !defined(__HIP_DEVICE_COMPILE__)")
-        table = self.colour_table() if not self.reg_jamp else []
-        w(f"static const double k_colour_table_{proc.tag}[] = {{" +
-          (", ".join(_lit(x) for x in table) if table else "0.0") + "};")
-        nvals = []
-        for a in range(self.k):
-            for b in range(self.k):
-                v = self.nmat[a][b]
-                nvals.append((v.numerator, v.denominator))
+        table = self.colour_table()
+        w(f"static const double k_colour_table_{proc.tag}[] = {{" + ", ".join(_lit(x) for x in table) + "};")
+        nvals = [(self.nmat[a][b].numerator, self.nmat[a][b].denominator)
+                 for a in range(self.k) for b in range(self.k)]
         w(f"static const long long k_num_{proc.tag}[] = {{" + ", ".join(str(x[0]) for x in nvals) + "};")
         w(f"static const long long k_den_{proc.tag}[] = {{" + ", ".join(str(x[1]) for x in nvals) + "};")
+        nt = 64 * nwave
         w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, int64_t n, double* out, "
           f"const double* cmat, double scale, hipStream_t s) {{")
-        w("  const dim3 grid((unsigned)((n + 63) / 64)), block(64);")
+        w(f"  const dim3 grid((unsigned)((n + 63) / 64)), block({nt});")
         w("  if (prec == 0)")
-        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_kernel<double>, grid, block, 0, s, mom, n, out, cmat, scale);")
+        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_f64, grid, block, 0, s, mom, n, out, cmat, scale);")
         w("  else")
-        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_kernel<float>, grid, block, 0, s, mom, n, out, cmat, scale);")
+        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mom, n, out, cmat, scale);")
         w("  return hipGetLastError();")
         w("}")
         nhel = 2 * sum(p.ncfg for p in self.pats)
         w(f"extern const heget_proc_desc heget_desc_{proc.tag} = {{")
         w(f"  \"{proc.spec}\", {proc.n}, {len(dag.amps)}, {self.k}, {nhel}, {1 << proc.n},")
         w(f"  {len(table)}, k_colour_table_{proc.tag}, k_num_{proc.tag}, k_den_{proc.tag},")
-        w(f"  {self.flops_per_event}LL, launch_{proc.tag}}};")
+        w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{proc.tag}}};")
         w("#endif")
         return "\n".join(lines) + "\n"

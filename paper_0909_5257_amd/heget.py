@@ -22,6 +22,12 @@ PRECISIONS = {"fp64": HEGET_FP64, "mixed": HEGET_MIXED}
 _lib = None
 
 
+class BatchItem(ctypes.Structure):
+    """heget_batch_item of include/heget.h."""
+    _fields_ = [("process", ctypes.c_void_p), ("momenta", ctypes.c_void_p),
+                ("n_events", ctypes.c_int64), ("me2", ctypes.c_void_p)]
+
+
 class HegetError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {lib().heget_status_string(status).decode()} (status {status})")
@@ -52,6 +58,8 @@ def lib():
     L.heget_destroy_process.restype = None
     L.heget_status_string.argtypes = [i32]
     L.heget_status_string.restype = ctypes.c_char_p
+    L.heget_matrix_elements_batch.argtypes = [ctypes.POINTER(BatchItem), i32, dbl, i32, vp]
+    L.heget_matrix_elements_batch.restype = i32
     L.heget_num_processes.argtypes = []
     L.heget_num_processes.restype = i32
     L.heget_process_spec.argtypes = [i32]
@@ -135,3 +143,20 @@ class Process:
             stream = torch.cuda.current_stream(momenta.device)
         self.matrix_elements_ptr(momenta.data_ptr(), n, alpha_s, out.data_ptr(), stream.cuda_stream)
         return out
+
+
+def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream=None):
+    """Fused uneven batch: items = [(Process, momenta tensor, out tensor), ...] on the GPU."""
+    import torch
+    arr = (BatchItem * len(items))()
+    for i, (proc, mom, out) in enumerate(items):
+        if mom.dtype != torch.float64 or not mom.is_cuda or not mom.is_contiguous():
+            raise TypeError("momenta must be contiguous float64 GPU tensors")
+        if mom.dim() != 3 or mom.shape[1:] != (proc.n_ext, 4) or out.shape[0] != mom.shape[0]:
+            raise ValueError("bad momenta/output shape")
+        arr[i] = BatchItem(proc.handle.value, mom.data_ptr(), mom.shape[0], out.data_ptr())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().heget_matrix_elements_batch(arr, len(items), alpha_s, int(use_graph),
+                                             ctypes.c_void_p(stream.cuda_stream)),
+           "heget_matrix_elements_batch")

@@ -62,7 +62,7 @@ def test_helicity_patterns(spec, n_hel):
 def test_every_diagram_has_a_colour_class():
     dag = Dag(parse("g g > g g g g"))
     amps = list(range(len(dag.amps)))
-    classes = colour_classes(dag, amps)
+    classes = colour_classes({i: a.coef for i, a in enumerate(dag.amps)}, amps)
     assert sum(len(m) for _, m in classes) == len(amps)
     # every cubic tree of 6 gluons is its own class: (2*6-5)!! = 105
     assert len(classes) == 105
@@ -114,3 +114,29 @@ def test_library_registry_and_status_strings():
     assert L.heget_create_process(None, 0, ctypes.byref(h)) == 1
     assert L.heget_create_process(b"g g > g g", 7, ctypes.byref(h)) == 1
     assert L.heget_matrix_elements(None, None, 0, 0.118, None, None) == 1
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g", "g g > g g g g", "u u~ > g g g g", "u u > u u g", "u u > u u g g"])
+def test_reduced_colour_space_is_exact(spec):
+    """y^H W y in the reduced space equals J^H N J in the paper's basis for arbitrary amplitudes."""
+    from paper_0909_5257_amd.gen.reduce import ColourSpace
+    dag = Dag(parse(spec))
+    nmat = dag.colour_matrix()
+    cs = ColourSpace(dag, nmat)
+    rng = np.random.default_rng(5)
+    k = len(dag.basis)
+    nf = np.array([[float(x) for x in r] for r in nmat])
+    w = np.array([[float(x) for x in r] for r in cs.w])
+    for _ in range(3):
+        amp = rng.normal(size=len(dag.amps)) + 1j * rng.normal(size=len(dag.amps))
+        jv = np.zeros(k, complex)
+        yv = np.zeros(cs.dim, complex)
+        for i, a in enumerate(dag.amps):
+            for idx, v in a.coef.items():
+                jv[idx] += v * amp[i]
+            for idx, v in cs.vector(a.coef).items():
+                yv[idx] += float(v) * amp[i]
+        q_full = (jv @ nf @ jv.conj()).real
+        q_red = (yv @ w @ yv.conj()).real
+        assert abs(q_red / q_full - 1) < 1e-13
+    assert cs.dim <= k

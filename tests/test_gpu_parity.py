@@ -78,6 +78,9 @@ def test_parity_small(torch_dev, spec, n, precision):
     ("g g > g g", 65536, 64),
     ("u u~ > g g g g", 1 << 20, 16),
     ("u u > u u g g", 1 << 20, 16),
+    ("g g > g g g g", 1 << 21, 16),
+    ("u u~ > g g g g g", 1 << 20, 8),
+    ("u u > u u g g g", 1 << 18, 6),
 ])
 def test_parity_full_size_sampled(torch_dev, spec, n_full, n_sample):
     """Workload-size launches, compared with the oracle on sampled events."""

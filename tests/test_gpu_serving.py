@@ -1,0 +1,77 @@
+"""Continuous-batching server: results identical alone and in the mix, admission by HBM budget."""
+import numpy as np
+import pytest
+
+from phasespace import KIN_C5, generate_events
+
+pytestmark = pytest.mark.gpu
+
+SPECS = ["g g > g g g", "u u~ > g g g g", "u u > u u g g", "g g > g g g g"]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pool():
+    out = {}
+    for i, s in enumerate(SPECS):
+        nf = len(s.split(">")[1].split())
+        out[s] = generate_events(5000, nf, KIN_C5, seed=11, stream=i)
+    return out
+
+
+def _alone(torch, spec, mom, precision):
+    from paper_0909_5257_amd.heget import Process
+    p = torch.from_numpy(mom).to("cuda")
+    r = Process(spec, precision).matrix_elements(p, 0.118)
+    torch.cuda.synchronize()
+    return r.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_results_same_alone_and_served(torch_dev, precision):
+    from paper_0909_5257_amd.serving import Server, latency_summary, run_poisson
+    pool = _pool()
+    rng0 = np.random.default_rng(3)
+
+    def workload(rng):
+        spec = SPECS[rng.integers(len(SPECS))]
+        n = int(2 ** rng.uniform(8, 12))
+        lo = int(rng.integers(0, 5000 - n))
+        return spec, pool[spec][lo:lo + n]
+
+    server = Server(SPECS, precisions=(precision,), hbm_budget_bytes=2 << 20, n_streams=4)
+    reqs, wall = run_poisson(server, workload, rate_hz=2000.0, n_requests=40, seed=int(rng0.integers(1 << 30)),
+                             precision=precision)
+    assert all(r.error is None for r in reqs)
+    for r in reqs:
+        ref = _alone(torch_dev, r.spec, r.momenta, precision)
+        assert np.array_equal(r.result, ref), (r.rid, r.spec)
+    s = latency_summary(reqs)
+    print(f"[serving] {precision}: {s}", flush=True)
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_budget_admission_and_oversize_isolation(torch_dev):
+    from paper_0909_5257_amd.serving import Server
+    pool = _pool()
+    spec = "u u~ > g g g g"
+    one = pool[spec][:1000]
+    budget = int(1.5 * (one.nbytes + 8 * 1000))       # room for one request at a time
+    server = Server([spec], precisions=("fp64",), hbm_budget_bytes=budget, n_streams=4)
+    reqs = [server.submit(spec, one) for _ in range(3)]
+    big = server.submit(spec, pool[spec])               # does not fit the budget at all
+    peak = 0
+    while not server.idle():
+        server.step()
+        peak = max(peak, len(server.running))
+    assert peak == 1                                   # admission held the budget
+    assert big.error is not None and big.result is None
+    ref = _alone(torch_dev, spec, one, "fp64")
+    for r in reqs:
+        assert r.error is None and np.array_equal(r.result, ref)
