@@ -21,9 +21,9 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-GEN_DIR = os.path.join(CSRC, "generated")
-BUILD_DIR = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libheget.so")
+GEN_DIR = os.environ.get("HEGET_GEN_DIR", os.path.join(CSRC, "generated"))
+BUILD_DIR = os.environ.get("HEGET_BUILD_DIR", os.path.join(ROOT, "_build"))
+LIB = os.environ.get("HEGET_LIB_OUT", os.path.join(HERE, "libheget.so"))
 
 # The processes of the paper's Table 1 whose kernels are compiled in.
 PROCESSES = [
@@ -40,6 +40,11 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
 ]
+for _prec in ("double", "float"):
+    _env = os.environ.get(f"HEGET_GROUP_BUDGET_{'F64' if _prec == 'double' else 'F32'}")
+    if _env:
+        from .gen import emit as _emit
+        _emit.GROUP_BUDGET[_prec] = int(_env)
 
 
 def generate(specs, verbose=True):

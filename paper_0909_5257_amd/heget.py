@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libheget.so")
+LIB_PATH = os.environ.get("HEGET_LIB", os.path.join(HERE, "libheget.so"))
 
 HEGET_OK = 0
 HEGET_FP64 = 0

@@ -6,8 +6,21 @@ from phasespace import KIN_C2, generate_events
 
 pytestmark = pytest.mark.gpu
 
+# Processes whose kernel spreads one event's colour vector over four waves add
+# into it with float64 LDS atomics: their results agree with a lone launch to
+# float64 rounding, not bit for bit.  All other kernels are deterministic.
+COOPERATIVE = {"u u~ > g g g g g"}
+
 FUSED = ["u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
          "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g"]
+
+
+def _same(spec, r, o, what=""):
+    import torch
+    if spec in COOPERATIVE:
+        assert torch.max(torch.abs(o / r - 1.0)).item() < 1e-13, (spec, what)
+    else:
+        assert torch.equal(r, o), (spec, what)
 
 
 @pytest.fixture(scope="module")
@@ -39,8 +52,8 @@ def test_batch_equals_individual(torch_dev, precision):
     outs = [torch.full((x.shape[0],), -1.0, dtype=torch.float64, device="cuda") for _, x in inputs]
     matrix_elements_batch([(p, x, o) for p, (_, x), o in zip(procs, inputs, outs)], 0.118)
     torch.cuda.synchronize()
-    for r, o in zip(ref, outs):
-        assert torch.equal(r, o)
+    for (spec, _), r, o in zip(inputs, ref, outs):
+        _same(spec, r, o)
 
 
 def test_batch_graph_replays(torch_dev):
@@ -58,5 +71,5 @@ def test_batch_graph_replays(torch_dev):
         torch.cuda.synchronize()
         matrix_elements_batch(items, 0.118, use_graph=True)
         torch.cuda.synchronize()
-        for r, o in zip(ref, outs):
-            assert torch.equal(r, o), f"replay {rep}"
+        for (spec, _), r, o in zip(inputs, ref, outs):
+            _same(spec, r, o, f"replay {rep}")

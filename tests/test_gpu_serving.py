@@ -64,8 +64,8 @@ def test_budget_admission_and_oversize_isolation(torch_dev):
     one = pool[spec][:1000]
     budget = int(1.5 * (one.nbytes + 8 * 1000))       # room for one request at a time
     server = Server([spec], precisions=("fp64",), hbm_budget_bytes=budget, n_streams=4)
-    reqs = [server.submit(spec, one) for _ in range(3)]
-    big = server.submit(spec, pool[spec])               # does not fit the budget at all
+    reqs = [server.submit(spec, one, "fp64") for _ in range(3)]
+    big = server.submit(spec, pool[spec], "fp64")               # does not fit the budget at all
     peak = 0
     while not server.idle():
         server.step()
