@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48, help="0 disables the serving run")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -189,6 +191,15 @@ def main():
 
     import torch
     from paper_0909_5257_amd.heget import Process
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 17            # float64 elements
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
 
     workload = [(s, (n >> 6 if args.quick else n), st) for s, n, st in WORKLOAD]
     inputs = make_inputs(workload)

@@ -129,6 +129,32 @@ typedef struct {
 heget_status heget_matrix_elements_batch(const heget_batch_item* items, int n_items, double alpha_s,
                                          int use_graph, void* stream);
 
+/* Precision of the colour contraction in heget_colour_quadratic_form. */
+typedef enum {
+  HEGET_COLOUR_FP64 = 0,    /* float64 GEMM */
+  HEGET_COLOUR_FP32 = 1,    /* float32 GEMM on the matrix cores */
+  HEGET_COLOUR_BF16X3 = 2   /* bf16 hi/lo split, three products, float32 accumulate */
+} heget_colour_mode;
+
+/* Colour quadratic form of eq. (color-averaged-amplitude) for many amplitude
+ * vectors at once, written as a GEMM: with the real and imaginary parts of J
+ * as separate rows X (2R x K), Y = X N and q_r = X_2r.Y_2r + X_2r+1.Y_2r+1.
+ * This is the colour step of the paper in its own basis, offered for precision
+ * and speed studies of the contraction (the process kernels do the same sum in
+ * an exactly reduced colour space).
+ *   n_colours     K > 0.
+ *   colour_matrix DEVICE float64 K x K, symmetric (e.g. heget_color_matrix values).
+ *   jamp          DEVICE float64 [rows][2][K]: Re J then Im J of each row.
+ *   rows          number of amplitude vectors R, 0 <= R <= 2^30.
+ *   mode          HEGET_COLOUR_FP64 / _FP32 / _BF16X3.
+ *   q             DEVICE float64 [rows], written.
+ *   stream        hipStream_t (NULL: default stream).
+ * Work space is taken and returned in stream order.  The row-wise dot is always
+ * accumulated in float64 against the float64 J.  Errors: HEGET_E_INVALID_ARG,
+ * HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
+heget_status heget_colour_quadratic_form(int n_colours, const double* colour_matrix, const double* jamp,
+                                         int64_t rows, heget_colour_mode mode, double* q, void* stream);
+
 /* Release a handle and its device state.  NULL is ignored.  The caller must
  * make sure no queued work still uses the handle. */
 void heget_destroy_process(heget_process_t p);

@@ -30,6 +30,9 @@ PROCESSES = [
     "g g > g g", "g g > g g g", "g g > g g g g",
     "u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
     "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g",
+    # crossed subprocesses: same diagram and colour counts as u u~ > n g
+    "u g > u g", "u g > u g g", "u g > u g g g",
+    "u u~ > u u~",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -40,6 +43,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
 ]
+for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS"):
+    if os.environ.get("HEGET_" + _name):
+        from .gen import emit as _emit
+        setattr(_emit, _name, int(os.environ["HEGET_" + _name]))
 for _prec in ("double", "float"):
     _env = os.environ.get(f"HEGET_GROUP_BUDGET_{'F64' if _prec == 'double' else 'F32'}")
     if _env:
@@ -111,7 +118,7 @@ def _compile(src, extra, force=False):
 def build(specs=None, jobs=None, resource_usage=False, verbose=True, force=False):
     specs = specs or PROCESSES
     files, reg = generate(specs, verbose)
-    srcs = [os.path.join(CSRC, "heget.cpp"), reg] + files
+    srcs = [os.path.join(CSRC, "heget.cpp"), os.path.join(CSRC, "colour_gemm.cpp"), reg] + files
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     objs = []
@@ -125,7 +132,8 @@ def build(specs=None, jobs=None, resource_usage=False, verbose=True, force=False
             if resource_usage and log:
                 print(log, flush=True)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + sorted(objs)
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + sorted(objs) + \
+        ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {res.stderr[-4000:]}")

@@ -39,6 +39,7 @@ FLOPS = {   # real floating-point operations per call, counted from the routines
 
 REG_Y_MAX = 64          # colour spaces up to this size are handled by one wave per workgroup
 CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one non-inlined chunk function
+COOP_CHUNK_FLOPS = 20000  # the same for the four-wave kernels (finer, so waves can be balanced)
 COOP_WAVES = 4          # waves per workgroup in the LDS (cooperative) mode
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 
@@ -355,7 +356,7 @@ class Emitter:
             cur.append(gi)
             cur_flops += b.flops
             open_cls = any(last_group[c] > gi for c, _, _ in groups[gi])
-            if cur_flops >= CHUNK_FLOPS and not open_cls:
+            if cur_flops >= (COOP_CHUNK_FLOPS if self.coop else CHUNK_FLOPS) and not open_cls:
                 chunks.append(cur)
                 cur, cur_flops = [], 0
         if cur:
@@ -407,12 +408,12 @@ class Emitter:
             total_flops += flops
         nwave = COOP_WAVES if self.coop else 1
         if nwave > 1:
-            acc, wv = 0, 0
-            for c in out:
-                if wv < nwave - 1 and acc >= (wv + 1) * total_flops / nwave:
-                    wv += 1
+            # longest chunk first onto the least loaded wave
+            load = [0] * nwave
+            for c in sorted(out, key=lambda c: -c[3]):
+                wv = min(range(nwave), key=lambda v: load[v])
                 c[2] = wv
-                acc += c[3]
+                load[wv] += c[3]
         cflops = total_flops + 2 * self.kdim * (self.kdim + 1)
         self.flops[prec] += cflops * pat.ncfg
         if prec == "double":

@@ -60,6 +60,8 @@ def lib():
     L.heget_status_string.restype = ctypes.c_char_p
     L.heget_matrix_elements_batch.argtypes = [ctypes.POINTER(BatchItem), i32, dbl, i32, vp]
     L.heget_matrix_elements_batch.restype = i32
+    L.heget_colour_quadratic_form.argtypes = [i32, vp, vp, i64, i32, vp, vp]
+    L.heget_colour_quadratic_form.restype = i32
     L.heget_num_processes.argtypes = []
     L.heget_num_processes.restype = i32
     L.heget_process_spec.argtypes = [i32]
@@ -160,3 +162,26 @@ def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream
     _check(lib().heget_matrix_elements_batch(arr, len(items), alpha_s, int(use_graph),
                                              ctypes.c_void_p(stream.cuda_stream)),
            "heget_matrix_elements_batch")
+
+
+COLOUR_MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def colour_quadratic_form(nmat, jamp, mode: str = "fp64", out=None, stream=None):
+    """q_r = J_r N J_r^* for device tensors nmat [K, K] and jamp [R, 2, K] (float64)."""
+    import torch
+    if nmat.dtype != torch.float64 or jamp.dtype != torch.float64 or not (nmat.is_cuda and jamp.is_cuda):
+        raise TypeError("float64 GPU tensors required")
+    k = nmat.shape[0]
+    if nmat.shape != (k, k) or jamp.dim() != 3 or jamp.shape[1:] != (2, k):
+        raise ValueError("nmat must be [K, K] and jamp [R, 2, K]")
+    nmat, jamp = nmat.contiguous(), jamp.contiguous()
+    rows = jamp.shape[0]
+    if out is None:
+        out = torch.empty(rows, dtype=torch.float64, device=jamp.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().heget_colour_quadratic_form(k, nmat.data_ptr(), jamp.data_ptr(), rows, COLOUR_MODES[mode],
+                                             out.data_ptr(), ctypes.c_void_p(stream.cuda_stream)),
+           "heget_colour_quadratic_form")
+    return out

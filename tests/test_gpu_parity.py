@@ -24,6 +24,7 @@ SMALL_CASES = [
     ("g g > g g", 200), ("g g > g g g", 131), ("g g > g g g g", 40),
     ("u u~ > g g", 200), ("u u~ > g g g", 131), ("u u~ > g g g g", 80), ("u u~ > g g g g g", 12),
     ("u u > u u", 200), ("u u > u u g", 131), ("u u > u u g g", 80), ("u u > u u g g g", 8),
+    ("u g > u g", 200), ("u g > u g g", 131), ("u g > u g g g", 64), ("u u~ > u u~", 200),
 ]
 
 

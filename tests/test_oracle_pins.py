@@ -111,6 +111,22 @@ def test_closed_form_uu_uu():
     np.testing.assert_allclose(oracle_me2("u u > u u", p, ALPHA_S), ref, rtol=1e-13)
 
 
+def test_closed_form_ug_ug():
+    """Crossing of u u~ > g g: ug -> ug = g^4 [-(4/9)(s^2+u^2)/(su) + (s^2+u^2)/t^2]."""
+    p = _events("u g > u g", 64, kin=KIN_C1)
+    s, t, u = _mandelstam(p)
+    ref = G2 ** 2 * (-(4 / 9) * (s * s + u * u) / (s * u) + (s * s + u * u) / t ** 2)
+    np.testing.assert_allclose(oracle_me2("u g > u g", p, ALPHA_S), ref, rtol=1e-13)
+
+
+def test_closed_form_uubar_uubar():
+    """Identical-flavour annihilation plus scattering, with the Fermi sign between them."""
+    p = _events("u u~ > u u~", 64, kin=KIN_C1)
+    s, t, u = _mandelstam(p)
+    ref = G2 ** 2 * ((4 / 9) * ((s * s + u * u) / t ** 2 + (u * u + t * t) / s ** 2) - (8 / 27) * u * u / (s * t))
+    np.testing.assert_allclose(oracle_me2("u u~ > u u~", p, ALPHA_S), ref, rtol=1e-13)
+
+
 def test_closed_form_90_degrees():
     """At 90 degrees in the CM frame: 30.375 g^4, ~1.037 g^4 and ~3.26 g^4."""
     e = 250.0
