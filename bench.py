@@ -172,6 +172,86 @@ def serving_run(n_requests, rate_hz=2000.0, seed=11):
     return served
 
 
+def _timed(torch, fn, steps, warmup):
+    """Average milliseconds of fn() over steps calls (HIP events on the current stream)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def helicity_mc_run(torch, workload, dev_inputs, steps, warmup):
+    """One drawn helicity configuration per event (the paper's per-event workload, section 3.2)."""
+    from phasespace import random_helicities
+    from paper_0909_5257_amd.heget import Process
+    out = {}
+    for (spec, n, stream), x in zip(workload, dev_inputs):
+        hel = torch.from_numpy(random_helicities(n, x.shape[1], seed=0, stream=stream)).to("cuda")
+        res = torch.empty(n, dtype=torch.float64, device="cuda")
+        row = {}
+        for precision in ("fp64", "mixed"):
+            pr = Process(spec, precision)
+            ms = _timed(torch, lambda: pr.matrix_elements_helicity(x, hel, ALPHA_S, out=res), steps, warmup)
+            row[precision] = {"ms_per_launch": ms, "events_per_s": n / (ms * 1e-3)}
+        out[spec] = {"events": n, **row}
+        log(f"[bench] helicity MC {spec}: fp64 {row['fp64']['events_per_s']:.3e}, "
+            f"mixed {row['mixed']['events_per_s']:.3e} events/s")
+    return out
+
+
+def colour_gemm_run(torch, rows, steps, warmup):
+    """Colour quadratic form of g g > g g g g (K = 120) as a GEMM over rows (event, helicity) in three modes."""
+    from paper_0909_5257_amd.heget import Process, colour_quadratic_form
+    _, _, nval = Process("g g > g g g g", "fp64").color_matrix()
+    k = nval.shape[0]
+    nmat = torch.from_numpy(nval).to("cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    jamp = torch.randn((rows, 2, k), dtype=torch.float64, device="cuda", generator=g)
+    q = {m: torch.empty(rows, dtype=torch.float64, device="cuda") for m in ("fp64", "fp32", "bf16x3")}
+    res = {"rows": rows, "colours": k, "shape": f"[{2 * rows} x {k}] . [{k} x {k}] + row dot"}
+    flops = 2.0 * (2 * rows) * k * k + 2.0 * (2 * rows) * k
+    for m in q:
+        ms = _timed(torch, lambda: colour_quadratic_form(nmat, jamp, m, out=q[m]), steps, warmup)
+        res[m] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12}
+    for m in ("fp32", "bf16x3"):
+        res[m]["max_rel_err_vs_fp64"] = float(((q[m] - q["fp64"]).abs() / q["fp64"].abs()).max())
+    log(f"[bench] colour GEMM K={k} rows={rows}: " + ", ".join(f"{m} {res[m]['ms']:.2f} ms" for m in q))
+    del jamp
+    return res
+
+
+def integration_run(torch, n, steps, warmup):
+    """Device RAMBO + |M|^2 + cuts + weight sums for g g > g g g g at sqrt(s) U[300, 2000] GeV."""
+    from phasespace import KIN_C2, random_helicities, rambo_uniforms
+    from paper_0909_5257_amd import heget
+    spec = "g g > g g g g"
+    rs, u = rambo_uniforms(n, 4, KIN_C2, seed=0)
+    rs_d, u_d = torch.from_numpy(rs).to("cuda"), torch.from_numpy(u).to("cuda")
+    hel = torch.from_numpy(random_helicities(n, 6, seed=0)).to("cuda")
+    out = {"process": spec, "events": n, "cuts": "pT>20, |eta|<2.5, dR>0.4 (zero weight if failed)"}
+    for label, precision, h in (("fp64", "fp64", None), ("mixed", "mixed", None), ("mixed_helicity_mc", "mixed", hel)):
+        pr = heget.Process(spec, precision)
+        last = {}
+
+        def step():
+            last["r"] = heget.integrate_step(pr, rs_d, u_d, ALPHA_S, 20.0, 2.5, 0.4, helicity=h)
+        ms = _timed(torch, step, steps, warmup)
+        sums = last["r"][3].cpu().numpy()
+        mean = sums[0] / n
+        err = math.sqrt(max(sums[1] / n - mean * mean, 0.0) / (n - 1))
+        out[label] = {"ms_per_step": ms, "events_per_s": n / (ms * 1e-3), "sigma_hat_pb": mean,
+                      "stat_err_pb": err}
+        log(f"[bench] integration {label}: {n / (ms * 1e-3):.3e} events/s, sigma-hat {mean:.4g} +- {err:.2g} pb")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +261,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48, help="0 disables the serving run")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the helicity Monte Carlo, colour GEMM and integration measurements")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
     args = ap.parse_args()
@@ -251,6 +333,12 @@ def main():
                 errs[spec] = float(np.max(np.abs(out[idx] / ref - 1.0)))
             accuracy[precision] = errs
 
+    extras = {}
+    if not args.no_extras:
+        extras["helicity_mc"] = helicity_mc_run(torch, workload, dev_inputs, args.steps, args.warmup)
+        extras["colour_gemm_c3"] = colour_gemm_run(torch, workload[1][1], args.steps, args.warmup)
+        extras["integration"] = integration_run(torch, workload[1][1], args.steps, args.warmup)
+    del dev_inputs
     serving = serving_run(args.serving_requests) if args.serving_requests > 0 else None
     fused = None if args.no_fused else fused_run(args.steps)
 
@@ -279,6 +367,7 @@ def main():
         "max_rel_err_vs_oracle": accuracy,
         "serving": serving,
         "fused_batch": fused,
+        **extras,
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
     }

@@ -86,6 +86,24 @@ heget_status heget_process_info(heget_process_t p, int* n_ext, int* n_diagrams, 
 heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int64_t n_events, double alpha_s,
                                    double* me2, void* stream);
 
+/* One term of the helicity sum per event: the Monte Carlo helicity mode of the
+ * paper's program structure (section 3.2, steps 2 and 4), where each phase-space
+ * point carries one helicity configuration drawn on the host and only that
+ * configuration's colour-summed |J|^2 (eq. color-averaged-amplitude) is
+ * evaluated.
+ *   momenta, n_events, alpha_s, me2, stream  as for heget_matrix_elements.
+ *   helicity DEVICE pointer, int32 [n_events], read only: a bit pattern h in
+ *            [0, 2^n_ext) with bit i set when leg i has helicity +1 and clear
+ *            when it has -1 (the helicity of an incoming parton as it enters).
+ * me2[e] = 1/4 * sum_{alpha,beta} J_alpha(h_e) N_alpha,beta J_beta(h_e)^*, so that the
+ * sum over all 2^n_ext patterns equals heget_matrix_elements and 2^n_ext * me2
+ * is an unbiased estimate of it for uniformly drawn h.  Structural zeros give
+ * exactly 0; an h outside [0, 2^n_ext) gives NaN for that event.
+ * Errors: as heget_matrix_elements, plus HEGET_E_INVALID_ARG for a NULL
+ * helicity pointer. */
+heget_status heget_matrix_elements_helicity(heget_process_t p, const double* momenta, const int32_t* helicity,
+                                            int64_t n_events, double alpha_s, double* me2, void* stream);
+
 /* Exact colour matrix N_alpha,beta of eq. (color-matrix), including the
  * 1/(n_a n_b) colour average: N = num / den element-wise, row-major K x K, in
  * the colour basis of eq. (color-amplitude) (single traces with leg 0 first for
@@ -154,6 +172,68 @@ typedef enum {
  * HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
 heget_status heget_colour_quadratic_form(int n_colours, const double* colour_matrix, const double* jamp,
                                          int64_t rows, heget_colour_mode mode, double* q, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Phase space and integration on the device: steps 4 to 7 of the paper's
+ * program structure (section 3.2) for a partonic collision at given sqrt(s)
+ * (no parton densities).
+ * ------------------------------------------------------------------------- */
+
+/* Jet cuts of section 2.2 (eqs. cuts): every final parton must have
+ * pT > pt_min (GeV) and |eta| < eta_max; if delta_r_min > 0 every pair must
+ * also have Delta R = sqrt(d_eta^2 + d_phi^2) > delta_r_min (this replaces the
+ * paper's relative-pT cut).  All comparisons are strict. */
+typedef struct {
+  double pt_min;
+  double eta_max;
+  double delta_r_min;
+} heget_cuts;
+
+/* Massless RAMBO (Kleiss, Stirling, Ellis, Comput. Phys. Commun. 40 (1986) 359):
+ * turns 4 uniform numbers per final parton into n_final massless momenta in
+ * the partonic centre-of-mass frame summing to (sqrt_s, 0, 0, 0).
+ *   n_final   2..8.
+ *   sqrt_s    DEVICE float64 [n_events], partonic energy per event (GeV).
+ *   uniforms  DEVICE float64 [n_events][n_final][4] in (0, 1): per parton
+ *             (cos theta = 2u0 - 1, phi = 2 pi u1, q0 = -log(u2 u3)).
+ *   momenta   DEVICE float64 [n_events][n_final + 2][4], written: the two
+ *             beams (sqrt_s/2)(1, 0, 0, +-1), then the finals; (E, px, py, pz).
+ *   ps_weight DEVICE float64 [n_events] or NULL: the constant massless phase-
+ *             space volume (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!).
+ * Asynchronous on stream.  Errors: HEGET_E_INVALID_ARG, HEGET_E_DEVICE. */
+heget_status heget_rambo(int n_final, int64_t n_events, const double* sqrt_s, const double* uniforms,
+                         double* momenta, double* ps_weight, void* stream);
+
+/* Cut flags: pass[e] = 1 if event e's final partons (legs 2..n_ext-1 of
+ * momenta [n_events][n_ext][4], DEVICE) pass *cuts (HOST struct), else 0.
+ * pass is DEVICE uint8 [n_events].  Errors: HEGET_E_INVALID_ARG (n_ext outside
+ * 4..10, non-finite cuts, eta_max <= 0), HEGET_E_DEVICE. */
+heget_status heget_apply_cuts(int n_ext, int64_t n_events, const double* momenta, const heget_cuts* cuts,
+                              uint8_t* pass, void* stream);
+
+/* One integration step: RAMBO momenta from the uniforms, |M|^2 (summed over
+ * helicities, or for one helicity pattern per event when helicity != NULL,
+ * then scaled by 2^n_ext), the cuts, and the event weights of the partonic
+ * cross section
+ *     f_e = (hbar c)^2 * Phi_n(s_e) * |M|^2_e * pass_e / (2 s_e * S)   [pb]
+ * with S the product of factorials of identical final partons (the factor
+ * the paper puts on the phase space, remark after eq. phase-space), and their
+ * sums.  The mean of f over the events estimates sigma-hat at sqrt_s.
+ *   p, alpha_s   as for heget_matrix_elements; n_events >= 1.
+ *   sqrt_s, uniforms, helicity  DEVICE inputs as for heget_rambo and
+ *                heget_matrix_elements_helicity (helicity may be NULL).
+ *   cuts         HOST struct.
+ *   momenta      DEVICE float64 [n_events][n_ext][4], written (16-byte aligned).
+ *   me2          DEVICE float64 [n_events], written: |M|^2 (helicity term x 2^n_ext
+ *                is NOT applied here; it is the entry point's output).
+ *   weight       DEVICE float64 [n_events], written: f_e.
+ *   sums         DEVICE float64 [2], written: sum f_e and sum f_e^2, added in a
+ *                fixed order (identical on every run).
+ * Work space for block partials is taken and returned in stream order.
+ * Errors: HEGET_E_INVALID_ARG, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
+heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const double* sqrt_s, const double* uniforms,
+                                  const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
+                                  double* me2, double* weight, double* sums, void* stream);
 
 /* Release a handle and its device state.  NULL is ignored.  The caller must
  * make sure no queued work still uses the handle. */

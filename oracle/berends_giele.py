@@ -92,3 +92,52 @@ def trace_word_to_bg(word: tuple, root: int) -> tuple:
     i = word.index(root)
     rot = word[i + 1:] + word[:i]
     return rot
+
+
+def trace_colour_matrix(n: int) -> tuple:
+    """Colour matrix of the single-trace basis for n gluons, averaged over two initial colours.
+
+    Returns (words, N) with words the orderings of legs 0..n-2 (the last leg n-1 closes
+    every trace) and N[w, w'] = 1/64 sum over all colours of conj(Tr(t^w t^r)) Tr(t^w' t^r),
+    t = lambda/2.  The trace of n generators is built once as a tensor over its n positions;
+    a relabelling of the colour indices turns the sum for (w, w') into the sum of that tensor
+    against itself with the positions permuted by w^-1 w', so only (n-1)! sums are needed.
+    """
+    import itertools
+    from .colour import _chain_tensor
+    chain = _chain_tensor(n)                                  # [8]*n + [3, 3]
+    tr = np.einsum("...ii->...", chain)                       # Tr(t^{b1} ... t^{bn}), [8]*n
+    words = list(itertools.permutations(range(n - 1)))
+    rel = {}
+    for sigma in words:
+        perm = list(sigma) + [n - 1]                          # trace position k holds relabelled leg perm[k]
+        inv = [0] * n
+        for k, leg in enumerate(perm):
+            inv[leg] = k
+        moved = np.transpose(tr, axes=inv)                    # moved[b] = tr[b_perm(0), ..., b_perm(n-1)]
+        rel[sigma] = np.vdot(tr, moved) / 64.0
+    index = {w: i for i, w in enumerate(words)}
+    nmat = np.zeros((len(words), len(words)), dtype=np.complex128)
+    for w in words:
+        pos = {leg: k for k, leg in enumerate(w)}
+        for w2 in words:
+            nmat[index[w], index[w2]] = rel[tuple(pos[leg] for leg in w2)]
+    return words, nmat
+
+
+def bg_me2(spec: str, momenta: np.ndarray, alpha_s: float, nmat_cache: dict = {}) -> np.ndarray:
+    """Spin/colour averaged |M|^2 of an all-gluon process from Berends-Giele amplitudes.
+
+    |M|^2 = 1/4 * 2^n g^(2(n-2)) * sum_h sum_{w,w'} conj(A_w) N_{w w'} A_w'
+    (the full amplitude is g^(n-2) sum_w Tr(T^w T^r) A_w with T = sqrt2 t).  This route
+    shares nothing with the Feynman-diagram oracle beyond the external polarisations."""
+    proc = parse_process(spec)
+    n = proc.n
+    if n not in nmat_cache:
+        nmat_cache[n] = trace_colour_matrix(n)
+    words, nmat = nmat_cache[n]
+    amps = bg_amplitudes(spec, momenta)
+    a = np.stack([amps[w] for w in words], axis=-1)            # [H, N, K]
+    q = np.einsum("hek,kl,hel->e", a.conj(), nmat, a).real
+    g2 = 4.0 * np.pi * alpha_s
+    return 0.25 * (2.0 ** n) * g2 ** (n - 2) * q

@@ -43,10 +43,17 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
 ]
-for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS"):
+# tuning knobs of the kernel planner, overridable from the environment (HEGET_<NAME>); the
+# per-precision ones take "float64_value,float32_value"
+for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS", "TARGET_WAVES_PER_CU", "FORCE_WAVES", "INLINE_CHUNKS"):
     if os.environ.get("HEGET_" + _name):
         from .gen import emit as _emit
-        setattr(_emit, _name, int(os.environ["HEGET_" + _name]))
+        _val = os.environ["HEGET_" + _name]
+        if isinstance(getattr(_emit, _name), dict):
+            _d, _f = (int(x) for x in _val.split(","))
+            setattr(_emit, _name, {"double": _d, "float": _f})
+        else:
+            setattr(_emit, _name, int(_val))
 for _prec in ("double", "float"):
     _env = os.environ.get(f"HEGET_GROUP_BUDGET_{'F64' if _prec == 'double' else 'F32'}")
     if _env:
@@ -118,7 +125,8 @@ def _compile(src, extra, force=False):
 def build(specs=None, jobs=None, resource_usage=False, verbose=True, force=False):
     specs = specs or PROCESSES
     files, reg = generate(specs, verbose)
-    srcs = [os.path.join(CSRC, "heget.cpp"), os.path.join(CSRC, "colour_gemm.cpp"), reg] + files
+    srcs = [os.path.join(CSRC, "heget.cpp"), os.path.join(CSRC, "colour_gemm.cpp"),
+            os.path.join(CSRC, "phase_space.cpp"), reg] + files
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     objs = []

@@ -100,7 +100,26 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
   // 2: configurations with leg 0 at helicity -1 equal their all-flipped partners;
   // 1/4: initial spin average; g^(2(n-2)): couplings left out of the kernels.
   const double scale = 2.0 * 0.25 * std::pow(g2, p->desc->n_ext - 2);
-  hipError_t e = p->desc->launch(p->precision, momenta, n_events, me2, p->colour_table_dev, scale,
+  hipError_t e = p->desc->launch(p->precision, momenta, nullptr, n_events, me2, p->colour_table_dev, scale,
+                                 reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+}
+
+heget_status heget_matrix_elements_helicity(heget_process_t p, const double* momenta, const int32_t* helicity,
+                                            int64_t n_events, double alpha_s, double* me2, void* stream) {
+  if (!p) return HEGET_E_INVALID_ARG;
+  if (n_events < 0 || n_events > (int64_t(1) << 36)) return HEGET_E_INVALID_ARG;
+  if (!(alpha_s > 0.0) || !std::isfinite(alpha_s)) return HEGET_E_INVALID_ARG;
+  if (n_events == 0) return HEGET_OK;
+  if (!momenta || !helicity || !me2) return HEGET_E_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(momenta) & 15u) != 0) return HEGET_E_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HEGET_E_DEVICE;
+  if (dev != p->device) return HEGET_E_INVALID_ARG;
+  const double g2 = 4.0 * M_PI * alpha_s;
+  // one term of the helicity sum: 1/4 initial spin average and the couplings, no flip factor
+  const double scale = 0.25 * std::pow(g2, p->desc->n_ext - 2);
+  hipError_t e = p->desc->launch(p->precision, momenta, helicity, n_events, me2, p->colour_table_dev, scale,
                                  reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
 }
@@ -176,7 +195,7 @@ hipError_t enqueue_batch(DevicePool* pool, const heget_batch_item* items, int n,
     load[s] += cost(i);
     used[s] = true;
     const heget_process* p = items[i].process;
-    e = p->desc->launch(p->precision, items[i].momenta, items[i].n_events, items[i].me2, p->colour_table_dev,
+    e = p->desc->launch(p->precision, items[i].momenta, nullptr, items[i].n_events, items[i].me2, p->colour_table_dev,
                         item_scale(p->desc, alpha_s), pool->streams[s]);
     if (e != hipSuccess) return e;
   }
@@ -299,3 +318,22 @@ const char* heget_process_spec(int index) {
 }
 
 }  // extern "C"
+
+double heget_detail_final_symmetry(heget_process_t p) {
+  // prod over final-state species of (multiplicity)!
+  std::istringstream in(p->desc->spec);
+  std::string tok;
+  bool final_state = false;
+  std::map<std::string, int> count;
+  while (in >> tok) {
+    if (tok == ">") {
+      final_state = true;
+      continue;
+    }
+    if (final_state) ++count[tok];
+  }
+  double f = 1.0;
+  for (const auto& kv : count)
+    for (int i = 2; i <= kv.second; ++i) f *= (double)i;
+  return f;
+}

@@ -20,7 +20,8 @@ struct heget_proc_desc {
   const long long* colour_den;
   long long flops_per_event[2];  // floating-point operations one event executes (float64, mixed), incl. recomputation
   long long algo_flops_per_event;  // the same with every shared current counted once (roofline numerator)
-  hipError_t (*launch)(int precision, const double* mom, int64_t n, double* out,
+  // hel == nullptr: sum over helicities; otherwise one helicity bit pattern per event
+  hipError_t (*launch)(int precision, const double* mom, const int* hel, int64_t n, double* out,
                        const double* colour_table_dev, double scale, hipStream_t stream);
 };
 

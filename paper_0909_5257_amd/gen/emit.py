@@ -37,10 +37,16 @@ FLOPS = {   # real floating-point operations per call, counted from the routines
     "ext": 40, "psum": 4, "inv": 8, "class_add": 4, "jamp_add": 4,
 }
 
-REG_Y_MAX = 64          # colour spaces up to this size are handled by one wave per workgroup
-CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one non-inlined chunk function
-COOP_CHUNK_FLOPS = 20000  # the same for the four-wave kernels (finer, so waves can be balanced)
-COOP_WAVES = 4          # waves per workgroup in the LDS (cooperative) mode
+CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one chunk function
+# the same when several waves share a workgroup: finer for float32 so that eight waves balance
+COOP_CHUNK_FLOPS = {"double": 40000, "float": 20000}
+LDS_PER_CU = 160 * 1024   # bytes of LDS per compute unit (gfx950)
+# resident waves per CU the workgroup shape aims for.  float32 code fits 256 registers, so two
+# waves per SIMD hide each other's latency; float64 code needs more (the allocator keeps the
+# excess in AGPRs instead of scratch), so one wave per SIMD with the whole register file.
+TARGET_WAVES_PER_CU = {"double": 4, "float": 8}
+FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process and precision (for tuning)
+INLINE_CHUNKS = False     # inline the chunk functions into the kernel instead of calling them
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 
 SIZES = {   # 32-bit registers per value
@@ -307,11 +313,32 @@ class Emitter:
         self.kdim = self.cs.dim
         self.vectors = {i: self.cs.vector(a.coef) for i, a in enumerate(dag.amps)}
         self.pats = patterns(dag)
-        self.coop = self.kdim > REG_Y_MAX
-        self.cblock = next(b for b in (8, 6, 4, 3, 2, 1) if self.kdim % b == 0)
+        self.nwave = {prec: self.waves_per_workgroup(prec) for prec in ("double", "float")}
+        # colour-sum row blocks: the largest block size that still gives every wave two blocks
+        most = max(self.nwave.values())
+        divs = [b for b in (8, 6, 4, 3, 2, 1) if self.kdim % b == 0]
+        self.cblock = next((b for b in divs if most == 1 or self.kdim // b >= 2 * most), divs[-1])
         self.flops = {"double": 0, "float": 0}
         self.algo_flops = 0
         self.stats = {}
+
+    def lds_bytes(self, nwave: int) -> int:
+        """Static LDS of one workgroup: momenta and colour vector of 64 events (+ partial sums)."""
+        return (self.proc.n * 4 + self.kdim * 2) * 64 * 8 + (nwave * 64 * 8 if nwave > 1 else 0)
+
+    def waves_per_workgroup(self, prec: str) -> int:
+        """Fewest waves per 64-event workgroup that still put two waves on every SIMD.
+
+        The workgroup's LDS (mostly the colour vector) limits how many workgroups share a
+        compute unit; splitting each event group's diagram work over more waves raises the
+        number of resident waves without raising the LDS per event."""
+        if FORCE_WAVES:
+            return FORCE_WAVES
+        for w in (1, 2, 4, 8):
+            per_cu = LDS_PER_CU // self.lds_bytes(w)
+            if per_cu >= 1 and w * per_cu >= TARGET_WAVES_PER_CU[prec]:
+                return w
+        return 8
 
     # ------------------------------------------------------------------ groups
     def _plan(self, pat: Pattern, prec: str):
@@ -356,7 +383,7 @@ class Emitter:
             cur.append(gi)
             cur_flops += b.flops
             open_cls = any(last_group[c] > gi for c, _, _ in groups[gi])
-            if cur_flops >= (COOP_CHUNK_FLOPS if self.coop else CHUNK_FLOPS) and not open_cls:
+            if cur_flops >= (COOP_CHUNK_FLOPS[prec] if self.nwave[prec] > 1 else CHUNK_FLOPS) and not open_cls:
                 chunks.append(cur)
                 cur, cur_flops = [], 0
         if cur:
@@ -396,17 +423,18 @@ class Emitter:
                 for ci in sorted({c for c, _, _ in items if last_group[c] == gi}):
                     for a, sc in sorted(classes[ci][0].items()):
                         flops += FLOPS["jamp_add"]
-                        if self.coop:
+                        if self.nwave[prec] > 1:
                             w(f"  lds_add(&yl[{a}][0][lane], {_lit(sc)} * k{ci}.re); "
                               f"lds_add(&yl[{a}][1][lane], {_lit(sc)} * k{ci}.im);")
                         else:
                             w(f"  yl[{a}][0][lane] += {_lit(sc)} * k{ci}.re; yl[{a}][1][lane] += {_lit(sc)} * k{ci}.im;")
             name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_c{ki}"
-            src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+            qual = "__attribute__((always_inline)) inline" if INLINE_CHUNKS else "__noinline__"
+            src = (f"__device__ {qual} void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
                    + "\n".join(lines) + "\n}\n")
             out.append([name, src, 0, flops])
             total_flops += flops
-        nwave = COOP_WAVES if self.coop else 1
+        nwave = self.nwave[prec]
         if nwave > 1:
             # longest chunk first onto the least loaded wave
             load = [0] * nwave
@@ -467,15 +495,43 @@ class Emitter:
                     out.append(float(v))
         return out
 
-    def _kernel(self, prec: str, chunks_per_pattern) -> list:
+    def helicity_map(self) -> list:
+        """Per helicity bit pattern h (bit i set: leg i at +1) with leg 0 at +1: pattern << 16 | cfg, or -1.
+
+        -1 marks a structural zero (no diagram survives the quark chiralities); patterns with
+        leg 0 at -1 are looked up through their all-flipped partner, whose |M|^2 is the same."""
+        proc = self.proc
+        out = []
+        for h in range(1 << proc.n):
+            if not h & 1:
+                out.append(-1)          # never read: the kernel flips such patterns first
+                continue
+            lam = {i: (1 if (h >> i) & 1 else -1) for i in range(proc.n)}
+            code = -1
+            for pi, pat in enumerate(self.pats):
+                if all(_h_of_leg(proc, q, lam[q]) == hq for q, hq in pat.hq.items()):
+                    cfg = sum(1 << j for j, g in enumerate(pat.free_gluons) if lam[g] == 1)
+                    code = (pi << 16) | cfg
+                    break
+            out.append(code)
+        return out
+
+    def _kernel(self, prec: str, chunks_per_pattern, sampled: bool = False) -> list:
+        """The summed kernel me2_* (every helicity configuration), or with sampled=True the kernel
+        me2h_* that evaluates one given helicity configuration per event."""
         sfx = "f64" if prec == "double" else "f32"
-        args = ("const double* __restrict__ mom, int64_t nev, double* __restrict__ out, "
+        hel_arg = "const int* __restrict__ hel, " if sampled else ""
+        args = (f"const double* __restrict__ mom, {hel_arg}int64_t nev, double* __restrict__ out, "
                 "const double* __restrict__ cmat, double scale")
-        nwave = COOP_WAVES if self.coop else 1
+        nwave = self.nwave[prec]
         nt = 64 * nwave
         out = []
         w = out.append
-        w(f"__global__ __launch_bounds__({nt}) void me2_{sfx}({args}) {{")
+        # second bound: minimum waves per SIMD, so that the register allocator (kernel and the
+        # chunk functions it calls) stays within the occupancy the LDS allows
+        lds_waves_per_simd = (LDS_PER_CU // self.lds_bytes(nwave)) * nwave // 4
+        min_waves = max(1, min(TARGET_WAVES_PER_CU[prec] // 4, lds_waves_per_simd))
+        w(f"__global__ __launch_bounds__({nt}, {min_waves}) void me2{'h' if sampled else ''}_{sfx}({args}) {{")
         w("  const int lane = threadIdx.x & 63;")
         w("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
         w("  const int64_t ev = (int64_t)blockIdx.x * 64 + lane;")
@@ -488,10 +544,25 @@ class Emitter:
         w("#pragma unroll")
         w("      for (int j = 0; j < 4; ++j) pml[i][j][lane] = pm[i][j];")
         w("  }")
+        if sampled:
+            w("  int hcode = -2;                     // -2: helicity index out of range")
+            w("  {")
+            w("    int h = hel[evc];")
+            w("    if (h >= 0 && h < (1 << NEXT)) {")
+            w("      if (!(h & 1)) h = ~h & ((1 << NEXT) - 1);")
+            w("      hcode = HMAP[h];")
+            w("    }")
+            w("  }")
+            w("  const int my_pat = hcode >= 0 ? hcode >> 16 : -1;")
+            w("  const int my_cfg = hcode >= 0 ? hcode & 0xffff : 0;")
         w("  double q = 0.0;")
         for pi, (pat, chunks) in enumerate(zip(self.pats, chunks_per_pattern)):
-            w("#pragma unroll 1")
-            w(f"  for (int cfg = 0; cfg < {pat.ncfg}; ++cfg) {{")
+            if sampled:
+                w(f"  if (__syncthreads_or(my_pat == {pi})) {{")
+                w(f"    const int cfg = my_pat == {pi} ? my_cfg : 0;")
+            else:
+                w("#pragma unroll 1")
+                w(f"  for (int cfg = 0; cfg < {pat.ncfg}; ++cfg) {{")
             w(f"    for (int a = threadIdx.x; a < {self.kdim * 128}; a += {nt}) (&yl[0][0][0])[a] = 0.0;")
             w("    __syncthreads();")
             for v in range(nwave):
@@ -505,9 +576,15 @@ class Emitter:
                 if nwave > 1:
                     w("    }")
             w("    __syncthreads();")
-            w(f"    q += colour_sum_lds_part<{self.kdim}, {self.cblock}, {nwave}>(yl, lane, wave, cmat);")
+            part = f"colour_sum_lds_part<{self.kdim}, {self.cblock}, {nwave}>(yl, lane, wave, cmat)"
+            if sampled:
+                w(f"    const double part = {part};")
+                w(f"    if (my_pat == {pi}) q += part;")
+            else:
+                w(f"    q += {part};")
             w("    __syncthreads();")
             w("  }")
+        res = "(hcode == -2 ? __builtin_nan(\"\") : t * scale)" if sampled else "t * scale"
         if nwave > 1:
             w(f"  __shared__ double qsum[{nwave}][64];")
             w("  qsum[wave][lane] = q;")
@@ -515,10 +592,11 @@ class Emitter:
             w("  if (wave == 0) {")
             w("    double t = 0.0;")
             w(f"    for (int v = 0; v < {nwave}; ++v) t += qsum[v][lane];")
-            w("    if (ev < nev) out[ev] = t * scale;")
+            w(f"    if (ev < nev) out[ev] = {res};")
             w("  }")
         else:
-            w("  if (ev < nev) out[ev] = q * scale;")
+            w("  const double t = q;")
+            w(f"  if (ev < nev) out[ev] = {res};")
         w("}")
         return out
 
@@ -527,13 +605,13 @@ class Emitter:
         ns = f"p_{proc.tag}"
         chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
                   for prec in ("double", "float")}
-        nwave = COOP_WAVES if self.coop else 1
         lines = []
         w = lines.append
         w(f"// Generated by paper_0909_5257_amd.gen for the process \"{proc.spec}\".  Do not edit.")
         w(f"// diagrams {len(dag.amps)}, shared currents {len(dag.nodes) - proc.n}, colour basis {self.k}, "
           f"reduced colour space {self.kdim}, helicity patterns {len(self.pats)}, "
-          f"evaluated configurations {sum(p.ncfg for p in self.pats)}, waves per workgroup {nwave}")
+          f"evaluated configurations {sum(p.ncfg for p in self.pats)}, waves per workgroup "
+          f"{self.nwave['double']} (float64) / {self.nwave['float']} (mixed)")
         for prec, st in self.stats.items():
             for s in st:
                 w(f"// {prec} pattern {s['pattern']}: {s['amps']} amplitudes in {s['groups']} groups and "
@@ -547,13 +625,15 @@ class Emitter:
         w(f"constexpr int NEXT = {proc.n};")
         w(f"__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events")
         w(f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event")
+        w(f"__constant__ int HMAP[{1 << proc.n}] = {{" + ", ".join(str(x) for x in self.helicity_map()) + "};")
         w("")
         for prec in ("double", "float"):
             for pat_chunks in chunks[prec]:
                 for c in pat_chunks:
                     lines.append(c[1])
-        lines.extend(self._kernel("double", chunks["double"]))
-        lines.extend(self._kernel("float", chunks["float"]))
+        for prec in ("double", "float"):
+            lines.extend(self._kernel(prec, chunks[prec]))
+            lines.extend(self._kernel(prec, chunks[prec], sampled=True))
         w("")
         w(f"}}  // namespace {ns}")
         w("}  // namespace heget")
@@ -565,14 +645,21 @@ class Emitter:
                  for a in range(self.k) for b in range(self.k)]
         w(f"static const long long k_num_{proc.tag}[] = {{" + ", ".join(str(x[0]) for x in nvals) + "};")
         w(f"static const long long k_den_{proc.tag}[] = {{" + ", ".join(str(x[1]) for x in nvals) + "};")
-        nt = 64 * nwave
-        w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, int64_t n, double* out, "
-          f"const double* cmat, double scale, hipStream_t s) {{")
-        w(f"  const dim3 grid((unsigned)((n + 63) / 64)), block({nt});")
-        w("  if (prec == 0)")
-        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_f64, grid, block, 0, s, mom, n, out, cmat, scale);")
-        w("  else")
-        w(f"    hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mom, n, out, cmat, scale);")
+        w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, const int* hel, int64_t n, "
+          f"double* out, const double* cmat, double scale, hipStream_t s) {{")
+        w(f"  const dim3 grid((unsigned)((n + 63) / 64)), "
+          f"block(prec == 0 ? {64 * self.nwave['double']} : {64 * self.nwave['float']});")
+        w("  if (hel == nullptr) {")
+        w("    if (prec == 0)")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2_f64, grid, block, 0, s, mom, n, out, cmat, scale);")
+        w("    else")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mom, n, out, cmat, scale);")
+        w("  } else {")
+        w("    if (prec == 0)")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mom, hel, n, out, cmat, scale);")
+        w("    else")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mom, hel, n, out, cmat, scale);")
+        w("  }")
         w("  return hipGetLastError();")
         w("}")
         nhel = 2 * sum(p.ncfg for p in self.pats)

@@ -28,6 +28,11 @@ class BatchItem(ctypes.Structure):
                 ("n_events", ctypes.c_int64), ("me2", ctypes.c_void_p)]
 
 
+class Cuts(ctypes.Structure):
+    """heget_cuts of include/heget.h: pT_min (GeV), eta_max, Delta R_min (<= 0: no pair cut)."""
+    _fields_ = [("pt_min", ctypes.c_double), ("eta_max", ctypes.c_double), ("delta_r_min", ctypes.c_double)]
+
+
 class HegetError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {lib().heget_status_string(status).decode()} (status {status})")
@@ -50,6 +55,8 @@ def lib():
     L.heget_process_info.restype = i32
     L.heget_matrix_elements.argtypes = [vp, vp, i64, dbl, vp, vp]
     L.heget_matrix_elements.restype = i32
+    L.heget_matrix_elements_helicity.argtypes = [vp, vp, vp, i64, dbl, vp, vp]
+    L.heget_matrix_elements_helicity.restype = i32
     L.heget_color_matrix.argtypes = [vp, pi32, pi64, pi64, pdbl]
     L.heget_color_matrix.restype = i32
     L.heget_process_flops.argtypes = [vp, pi64]
@@ -62,6 +69,12 @@ def lib():
     L.heget_matrix_elements_batch.restype = i32
     L.heget_colour_quadratic_form.argtypes = [i32, vp, vp, i64, i32, vp, vp]
     L.heget_colour_quadratic_form.restype = i32
+    L.heget_rambo.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+    L.heget_rambo.restype = i32
+    L.heget_apply_cuts.argtypes = [i32, i64, vp, ctypes.POINTER(Cuts), vp, vp]
+    L.heget_apply_cuts.restype = i32
+    L.heget_integrate_step.argtypes = [vp, i64, vp, vp, vp, dbl, ctypes.POINTER(Cuts), vp, vp, vp, vp, vp]
+    L.heget_integrate_step.restype = i32
     L.heget_num_processes.argtypes = []
     L.heget_num_processes.restype = i32
     L.heget_process_spec.argtypes = [i32]
@@ -146,6 +159,28 @@ class Process:
         self.matrix_elements_ptr(momenta.data_ptr(), n, alpha_s, out.data_ptr(), stream.cuda_stream)
         return out
 
+    def matrix_elements_helicity(self, momenta, helicity, alpha_s: float, out=None, stream=None):
+        """One helicity term per event: helicity is an int32 device tensor [N] of bit patterns."""
+        import torch
+        if momenta.dtype != torch.float64 or not momenta.is_cuda:
+            raise TypeError("momenta must be a float64 tensor on the GPU")
+        if momenta.dim() != 3 or momenta.shape[1:] != (self.n_ext, 4):
+            raise ValueError(f"momenta must have shape [N, {self.n_ext}, 4]")
+        if helicity.dtype != torch.int32 or not helicity.is_cuda or helicity.shape != momenta.shape[:1]:
+            raise TypeError("helicity must be an int32 GPU tensor [N]")
+        momenta, helicity = momenta.contiguous(), helicity.contiguous()
+        n = momenta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(momenta.device)
+        _check(lib().heget_matrix_elements_helicity(self._h, ctypes.c_void_p(momenta.data_ptr()),
+                                                    ctypes.c_void_p(helicity.data_ptr()), n, alpha_s,
+                                                    ctypes.c_void_p(out.data_ptr()),
+                                                    ctypes.c_void_p(stream.cuda_stream)),
+               "heget_matrix_elements_helicity")
+        return out
+
 
 def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream=None):
     """Fused uneven batch: items = [(Process, momenta tensor, out tensor), ...] on the GPU."""
@@ -185,3 +220,63 @@ def colour_quadratic_form(nmat, jamp, mode: str = "fp64", out=None, stream=None)
                                              out.data_ptr(), ctypes.c_void_p(stream.cuda_stream)),
            "heget_colour_quadratic_form")
     return out
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, shape, what):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise TypeError(f"{what} must be a contiguous float64 GPU tensor of shape {tuple(shape)}")
+
+
+def rambo(sqrt_s, uniforms, stream=None):
+    """Device RAMBO: sqrt_s [N], uniforms [N, n_final, 4] -> (momenta [N, n_final + 2, 4], weight [N])."""
+    import torch
+    n, nf = uniforms.shape[0], uniforms.shape[1]
+    _dev_f64(sqrt_s, (n,), "sqrt_s")
+    _dev_f64(uniforms, (n, nf, 4), "uniforms")
+    mom = torch.empty((n, nf + 2, 4), dtype=torch.float64, device=uniforms.device)
+    w = torch.empty(n, dtype=torch.float64, device=uniforms.device)
+    _check(lib().heget_rambo(nf, n, sqrt_s.data_ptr(), uniforms.data_ptr(), mom.data_ptr(), w.data_ptr(),
+                             _stream_ptr(stream)), "heget_rambo")
+    return mom, w
+
+
+def apply_cuts(momenta, pt_min: float, eta_max: float, delta_r_min: float, stream=None):
+    """uint8 [N] pass flags of the jet cuts for momenta [N, n_ext, 4] on the GPU."""
+    import torch
+    n, n_ext = momenta.shape[0], momenta.shape[1]
+    _dev_f64(momenta, (n, n_ext, 4), "momenta")
+    out = torch.empty(n, dtype=torch.uint8, device=momenta.device)
+    cuts = Cuts(pt_min, eta_max, delta_r_min)
+    _check(lib().heget_apply_cuts(n_ext, n, momenta.data_ptr(), ctypes.byref(cuts), out.data_ptr(),
+                                  _stream_ptr(stream)), "heget_apply_cuts")
+    return out
+
+
+def integrate_step(proc: Process, sqrt_s, uniforms, alpha_s: float, pt_min: float, eta_max: float,
+                   delta_r_min: float, helicity=None, stream=None):
+    """One device integration step; returns (momenta, me2, weight, sums[2]) GPU tensors."""
+    import torch
+    n = uniforms.shape[0]
+    _dev_f64(sqrt_s, (n,), "sqrt_s")
+    _dev_f64(uniforms, (n, proc.n_ext - 2, 4), "uniforms")
+    if helicity is not None and (helicity.dtype != torch.int32 or not helicity.is_cuda or helicity.shape != (n,)):
+        raise TypeError("helicity must be an int32 GPU tensor [N]")
+    dev = uniforms.device
+    mom = torch.empty((n, proc.n_ext, 4), dtype=torch.float64, device=dev)
+    me2 = torch.empty(n, dtype=torch.float64, device=dev)
+    w = torch.empty(n, dtype=torch.float64, device=dev)
+    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    cuts = Cuts(pt_min, eta_max, delta_r_min)
+    _check(lib().heget_integrate_step(proc.handle, n, sqrt_s.data_ptr(), uniforms.data_ptr(),
+                                      None if helicity is None else helicity.data_ptr(), alpha_s,
+                                      ctypes.byref(cuts), mom.data_ptr(), me2.data_ptr(), w.data_ptr(),
+                                      sums.data_ptr(), _stream_ptr(stream)), "heget_integrate_step")
+    return mom, me2, w, sums

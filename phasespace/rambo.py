@@ -127,3 +127,24 @@ def generate_events(n_events: int, n_final: int, kin: Kinematics, seed: int,
         out[filled:filled + take, 2:, :] = fin[:take]
         filled += take
     return out
+
+
+def random_helicities(n_events: int, n_ext: int, seed: int, stream: int = 0) -> np.ndarray:
+    """Uniformly drawn helicity bit patterns int32 [N] (bit i set: leg i at helicity +1)."""
+    rng = np.random.Generator(np.random.PCG64([seed, stream, 0x68656c]))
+    return rng.integers(0, 1 << n_ext, size=n_events, dtype=np.int32)
+
+
+def rambo_uniforms(n_events: int, n_final: int, kin: Kinematics, seed: int, stream: int = 0):
+    """Raw inputs of one device RAMBO step: (sqrt_s float64 [N], uniforms float64 [N][n_final][4]).
+
+    sqrt_s is uniform in [sqrt_s_min, sqrt_s_max]; the uniforms lie in (0, 1).  No cut is applied:
+    an integration step gives events that fail the cuts zero weight."""
+    rng = np.random.Generator(np.random.PCG64([seed, stream, 0x72616d]))
+    if kin.sqrt_s_min == kin.sqrt_s_max:
+        rs = np.full(n_events, float(kin.sqrt_s_min))
+    else:
+        rs = kin.sqrt_s_min + (kin.sqrt_s_max - kin.sqrt_s_min) * rng.random(n_events)
+    u = rng.random((n_events, n_final, 4))
+    u = np.where(u > 0.0, u, 0.5)          # (0, 1): log(u2 u3) stays finite
+    return rs, u

@@ -140,3 +140,44 @@ def test_reduced_colour_space_is_exact(spec):
         q_red = (yv @ w @ yv.conj()).real
         assert abs(q_red / q_full - 1) < 1e-13
     assert cs.dim <= k
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g", "u u~ > g g g", "u u > u u g", "u g > u g g", "u u~ > u u~"])
+def test_helicity_map_covers_each_configuration_once(spec):
+    """The sampled-helicity table reaches every evaluated configuration from exactly one
+    leg-0-positive pattern, and its structural zeros are those of the oracle."""
+    from oracle import oracle_me2
+    from phasespace import KIN_C2, generate_events
+    dag = Dag(parse(spec))
+    em = Emitter(dag, dag.colour_matrix())
+    hmap = em.helicity_map()
+    n = dag.proc.n
+    codes = [hmap[h] for h in range(1 << n) if h & 1 and hmap[h] >= 0]
+    assert len(codes) == len(set(codes)) == sum(p.ncfg for p in em.pats)
+    p = generate_events(3, n - 2, KIN_C2, seed=4)
+    _, per_hel = oracle_me2(spec, p, 0.118, return_helicities=True)
+    for h in range(1 << n):
+        hp = h if h & 1 else ~h & ((1 << n) - 1)
+        # chirality zeros vanish identically in the oracle too (dynamic zeros such as
+        # all-but-one equal gluon helicities only to rounding, and are evaluated)
+        oracle_zero = bool(np.all(per_hel[h] == 0.0))
+        assert (hmap[hp] < 0) == oracle_zero, h
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g", "g g > g g g g", "u u~ > g g g g", "u u > u u g g g"])
+def test_workgroup_shape_fits_lds_and_meets_occupancy_target(spec):
+    """Every kernel's static LDS fits one CU and the chosen waves per workgroup reach the
+    precision's resident-wave target (or the largest shape is taken)."""
+    from paper_0909_5257_amd.gen import emit
+    dag = Dag(parse(spec))
+    em = Emitter(dag, dag.colour_matrix())
+    for prec in ("double", "float"):
+        w = em.nwave[prec]
+        lds = em.lds_bytes(w)
+        assert lds <= emit.LDS_PER_CU
+        per_cu = emit.LDS_PER_CU // lds
+        assert w * per_cu >= emit.TARGET_WAVES_PER_CU[prec] or w == 8
+        if w > 1:       # no smaller shape would have done
+            half = w // 2
+            assert half * (emit.LDS_PER_CU // em.lds_bytes(half)) < emit.TARGET_WAVES_PER_CU[prec]
+    assert em.kdim % em.cblock == 0

@@ -2,14 +2,13 @@
 import numpy as np
 import pytest
 
+from conftest import cooperative_processes
 from phasespace import KIN_C2, generate_events
 
 pytestmark = pytest.mark.gpu
 
-# Processes whose kernel spreads one event's colour vector over four waves add
-# into it with float64 LDS atomics: their results agree with a lone launch to
-# float64 rounding, not bit for bit.  All other kernels are deterministic.
-COOPERATIVE = {"u u~ > g g g g g"}
+# multi-wave kernels agree with a lone launch to float64 rounding, single-wave ones bit for bit
+COOPERATIVE = cooperative_processes()
 
 FUSED = ["u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
          "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g"]

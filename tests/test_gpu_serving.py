@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+from conftest import cooperative_processes
 from phasespace import KIN_C5, generate_events
 
 pytestmark = pytest.mark.gpu
@@ -49,9 +50,13 @@ def test_results_same_alone_and_served(torch_dev, precision):
     reqs, wall = run_poisson(server, workload, rate_hz=2000.0, n_requests=40, seed=int(rng0.integers(1 << 30)),
                              precision=precision)
     assert all(r.error is None for r in reqs)
+    coop = cooperative_processes()
     for r in reqs:
         ref = _alone(torch_dev, r.spec, r.momenta, precision)
-        assert np.array_equal(r.result, ref), (r.rid, r.spec)
+        if r.spec in coop:      # multi-wave kernel: float64 LDS atomics in any order
+            assert np.max(np.abs(r.result / ref - 1.0)) < 1e-13, (r.rid, r.spec)
+        else:
+            assert np.array_equal(r.result, ref), (r.rid, r.spec)
     s = latency_summary(reqs)
     print(f"[serving] {precision}: {s}", flush=True)
     assert s["p99_ms"] >= s["p50_ms"] > 0
@@ -74,4 +79,8 @@ def test_budget_admission_and_oversize_isolation(torch_dev):
     assert big.error is not None and big.result is None
     ref = _alone(torch_dev, spec, one, "fp64")
     for r in reqs:
-        assert r.error is None and np.array_equal(r.result, ref)
+        assert r.error is None
+        if spec in cooperative_processes():
+            assert np.max(np.abs(r.result / ref - 1.0)) < 1e-13
+        else:
+            assert np.array_equal(r.result, ref)
