@@ -227,6 +227,24 @@ def colour_gemm_run(torch, rows, steps, warmup):
     return res
 
 
+def gg5g_run(torch, n, steps, warmup):
+    """g g > g g g g g (7,245 diagrams, 720 colours), all helicities, both precisions."""
+    from phasespace import KIN_C2, generate_events
+    from paper_0909_5257_amd.heget import Process
+    spec = "g g > g g g g g"
+    x = torch.from_numpy(generate_events(n, 5, KIN_C2, seed=0, stream=5)).to("cuda")
+    res = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {"events": n}
+    for precision in ("fp64", "mixed"):
+        pr = Process(spec, precision)
+        ms = _timed(torch, lambda: pr.matrix_elements(x, ALPHA_S, out=res), steps, warmup)
+        flops = pr.flops_per_event()
+        out[precision] = {"ms_per_launch": ms, "events_per_s": n / (ms * 1e-3),
+                          "algorithmic_tflops": flops * n / (ms * 1e-3) / 1e12, "flops_per_event": flops}
+        log(f"[bench] {spec} {precision}: {n / (ms * 1e-3):.3e} events/s")
+    return out
+
+
 def integration_run(torch, n, steps, warmup):
     """Device RAMBO + |M|^2 + cuts + weight sums for g g > g g g g at sqrt(s) U[300, 2000] GeV."""
     from phasespace import KIN_C2, random_helicities, rambo_uniforms
@@ -338,6 +356,7 @@ def main():
         extras["helicity_mc"] = helicity_mc_run(torch, workload, dev_inputs, args.steps, args.warmup)
         extras["colour_gemm_c3"] = colour_gemm_run(torch, workload[1][1], args.steps, args.warmup)
         extras["integration"] = integration_run(torch, workload[1][1], args.steps, args.warmup)
+        extras["gg_5g"] = gg5g_run(torch, workload[1][1] >> 3, min(args.steps, 2), min(args.warmup, 1))
     del dev_inputs
     serving = serving_run(args.serving_requests) if args.serving_requests > 0 else None
     fused = None if args.no_fused else fused_run(args.steps)

@@ -167,9 +167,11 @@ typedef enum {
  *   mode          HEGET_COLOUR_FP64 / _FP32 / _BF16X3.
  *   q             DEVICE float64 [rows], written.
  *   stream        hipStream_t (NULL: default stream).
- * Work space is taken and returned in stream order.  The row-wise dot is always
- * accumulated in float64 against the float64 J.  Errors: HEGET_E_INVALID_ARG,
- * HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
+ * Work space (at most 1.25 times the bytes of jamp) is taken from and
+ * returned to the device's default stream-ordered memory pool; the first call
+ * on a device sets that pool to keep up to 16 GiB of freed memory cached for
+ * later calls.  The row-wise dot is always accumulated in float64 against the
+ * float64 J.  Errors: HEGET_E_INVALID_ARG, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
 heget_status heget_colour_quadratic_form(int n_colours, const double* colour_matrix, const double* jamp,
                                          int64_t rows, heget_colour_mode mode, double* q, void* stream);
 

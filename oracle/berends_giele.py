@@ -21,6 +21,8 @@ must equal A up to one process-wide constant.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 from . import lorentz as L
@@ -94,6 +96,7 @@ def trace_word_to_bg(word: tuple, root: int) -> tuple:
     return rot
 
 
+@functools.lru_cache(maxsize=None)
 def trace_colour_matrix(n: int) -> tuple:
     """Colour matrix of the single-trace basis for n gluons, averaged over two initial colours.
 
@@ -125,7 +128,7 @@ def trace_colour_matrix(n: int) -> tuple:
     return words, nmat
 
 
-def bg_me2(spec: str, momenta: np.ndarray, alpha_s: float, nmat_cache: dict = {}) -> np.ndarray:
+def bg_me2(spec: str, momenta: np.ndarray, alpha_s: float) -> np.ndarray:
     """Spin/colour averaged |M|^2 of an all-gluon process from Berends-Giele amplitudes.
 
     |M|^2 = 1/4 * 2^n g^(2(n-2)) * sum_h sum_{w,w'} conj(A_w) N_{w w'} A_w'
@@ -133,9 +136,7 @@ def bg_me2(spec: str, momenta: np.ndarray, alpha_s: float, nmat_cache: dict = {}
     shares nothing with the Feynman-diagram oracle beyond the external polarisations."""
     proc = parse_process(spec)
     n = proc.n
-    if n not in nmat_cache:
-        nmat_cache[n] = trace_colour_matrix(n)
-    words, nmat = nmat_cache[n]
+    words, nmat = trace_colour_matrix(n)
     amps = bg_amplitudes(spec, momenta)
     a = np.stack([amps[w] for w in words], axis=-1)            # [H, N, K]
     q = np.einsum("hek,kl,hel->e", a.conj(), nmat, a).real

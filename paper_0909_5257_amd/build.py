@@ -3,7 +3,7 @@
     python -m paper_0909_5257_amd.build [--only TAG ...] [--jobs N] [--resource-usage]
 
 Steps: for every supported process, build the shared-current DAG and the
-exact colour matrix, emit csrc/generated/proc_<tag>.hip and a registry, then
+exact colour matrix, emit csrc/generated/proc_<tag>_{f64,f32}.hip and a registry, then
 compile each translation unit with hipcc for gfx950 and link the shared
 library next to this file.
 """
@@ -28,6 +28,8 @@ LIB = os.environ.get("HEGET_LIB_OUT", os.path.join(HERE, "libheget.so"))
 # The processes of the paper's Table 1 whose kernels are compiled in.
 PROCESSES = [
     "g g > g g", "g g > g g g", "g g > g g g g",
+    # 7,245 diagrams, 720 colours: the paper could not compile it for its GPU
+    "g g > g g g g g",
     "u u~ > g g", "u u~ > g g g", "u u~ > g g g g", "u u~ > g g g g g",
     "u u > u u", "u u > u u g", "u u > u u g g", "u u > u u g g g",
     # crossed subprocesses: same diagram and colour counts as u u~ > n g
@@ -45,7 +47,8 @@ FLAGS = [
 ]
 # tuning knobs of the kernel planner, overridable from the environment (HEGET_<NAME>); the
 # per-precision ones take "float64_value,float32_value"
-for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS", "TARGET_WAVES_PER_CU", "FORCE_WAVES", "INLINE_CHUNKS"):
+for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS", "TARGET_WAVES_PER_CU", "FORCE_WAVES", "INLINE_CHUNKS",
+              "MERGE_WAVE_CHUNKS"):
     if os.environ.get("HEGET_" + _name):
         from .gen import emit as _emit
         _val = os.environ["HEGET_" + _name]
@@ -71,13 +74,19 @@ def generate(specs, verbose=True):
         t0 = time.time()
         dag = Dag(parse(spec))
         nmat = dag.colour_matrix()
-        src = Emitter(dag, nmat).emit()
-        path = os.path.join(GEN_DIR, f"proc_{dag.proc.tag}.hip")
-        _write_if_changed(path, src)
-        files.append(path)
+        srcs = Emitter(dag, nmat).emit()
+        for part, src in srcs.items():
+            path = os.path.join(GEN_DIR, f"proc_{dag.proc.tag}_{part}.hip")
+            _write_if_changed(path, src)
+            files.append(path)
         tags.append(dag.proc.tag)
         if verbose:
-            print(f"[gen] {spec:22s} -> {os.path.basename(path)} ({time.time() - t0:.1f}s)", flush=True)
+            print(f"[gen] {spec:22s} -> proc_{dag.proc.tag}_{{f64,f32}}.hip ({time.time() - t0:.1f}s)", flush=True)
+    # drop generated sources of processes (or layouts) this build does not contain
+    for name in os.listdir(GEN_DIR):
+        path = os.path.join(GEN_DIR, name)
+        if name.startswith("proc_") and name.endswith(".hip") and path not in files:
+            os.remove(path)
     reg = ['#include "heget_kernel_common.hpp"']
     reg += [f"extern const heget_proc_desc heget_desc_{t};" for t in tags]
     reg.append("extern const heget_proc_desc* const heget_registry[] = {")
@@ -130,6 +139,7 @@ def build(specs=None, jobs=None, resource_usage=False, verbose=True, force=False
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     objs = []
+    srcs = sorted(srcs, key=lambda p: -os.path.getsize(p))      # longest compiles start first
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_compile, s, extra, force): s for s in srcs}
         for fut in cf.as_completed(futs):

@@ -33,6 +33,13 @@ rocblas_handle handle_for(int dev) {
   rocblas_handle h = nullptr;
   if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
   g_handles[dev] = h;
+  // keep freed work space in the device's stream-ordered pool between calls instead of
+  // returning it to the driver at every synchronisation (re-mapping gigabytes per call)
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t keep = uint64_t(16) << 30;     // up to 16 GiB stays cached
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   return h;
 }
 
@@ -67,16 +74,20 @@ __global__ void split_matrix_bf16(const double* __restrict__ n, __hip_bfloat16* 
   y[2 * k * k + i] = hi;
 }
 
+// One wave per row: the 64 lanes read consecutive elements of the row (coalesced) and the
+// partial sums are combined with a butterfly over the wave.
 template <class T>
-__global__ void row_dot(const double* __restrict__ x, const T* __restrict__ y, int k, int64_t rows,
-                        double* __restrict__ q) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
+__global__ __launch_bounds__(256) void row_dot(const double* __restrict__ x, const T* __restrict__ y, int k,
+                                               int64_t rows, double* __restrict__ q) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;                      // whole waves leave together
   const double* xr = x + r * 2 * k;
   const T* yr = y + r * 2 * k;
   double s = 0.0;
-  for (int a = 0; a < 2 * k; ++a) s += xr[a] * (double)yr[a];
-  q[r] = s;
+  for (int a = lane; a < 2 * k; a += 64) s += xr[a] * (double)yr[a];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) q[r] = s;
 }
 
 inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -107,7 +118,7 @@ extern "C" heget_status heget_colour_quadratic_form(int k, const double* nmat, c
                       jamp, k, &zero, y, k) != rocblas_status_success)
       st = HEGET_E_DEVICE;
     else
-      hipLaunchKernelGGL(row_dot<double>, dim3(blocks(rows, 256)), dim3(256), 0, s, jamp, y, k, rows, q);
+      hipLaunchKernelGGL(row_dot<double>, dim3(blocks(rows, 4)), dim3(256), 0, s, jamp, y, k, rows, q);
     (void)hipFreeAsync(y, s);
   } else if (mode == HEGET_COLOUR_FP32) {
     float *x32 = nullptr, *n32 = nullptr, *y = nullptr;
@@ -128,7 +139,7 @@ extern "C" heget_status heget_colour_quadratic_form(int k, const double* nmat, c
                       k, &zero, y, k) != rocblas_status_success)
       st = HEGET_E_DEVICE;
     else
-      hipLaunchKernelGGL(row_dot<float>, dim3(blocks(rows, 256)), dim3(256), 0, s, jamp, y, k, rows, q);
+      hipLaunchKernelGGL(row_dot<float>, dim3(blocks(rows, 4)), dim3(256), 0, s, jamp, y, k, rows, q);
     (void)hipFreeAsync(x32, s);
     (void)hipFreeAsync(n32, s);
     (void)hipFreeAsync(y, s);
@@ -155,7 +166,7 @@ extern "C" heget_status heget_colour_quadratic_form(int k, const double* nmat, c
                         rocblas_gemm_algo_standard, 0, 0) != rocblas_status_success)
       st = HEGET_E_DEVICE;
     else
-      hipLaunchKernelGGL(row_dot<float>, dim3(blocks(rows, 256)), dim3(256), 0, s, jamp, y, k, rows, q);
+      hipLaunchKernelGGL(row_dot<float>, dim3(blocks(rows, 4)), dim3(256), 0, s, jamp, y, k, rows, q);
     (void)hipFreeAsync(xb, s);
     (void)hipFreeAsync(nb, s);
     (void)hipFreeAsync(y, s);

@@ -47,6 +47,7 @@ LDS_PER_CU = 160 * 1024   # bytes of LDS per compute unit (gfx950)
 TARGET_WAVES_PER_CU = {"double": 4, "float": 8}
 FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process and precision (for tuning)
 INLINE_CHUNKS = False     # inline the chunk functions into the kernel instead of calling them
+MERGE_WAVE_CHUNKS = False  # one called function per wave holding all of that wave's chunks
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 
 SIZES = {   # 32-bit registers per value
@@ -432,7 +433,7 @@ class Emitter:
             qual = "__attribute__((always_inline)) inline" if INLINE_CHUNKS else "__noinline__"
             src = (f"__device__ {qual} void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
                    + "\n".join(lines) + "\n}\n")
-            out.append([name, src, 0, flops])
+            out.append([name, src, 0, flops, lines])
             total_flops += flops
         nwave = self.nwave[prec]
         if nwave > 1:
@@ -442,6 +443,24 @@ class Emitter:
                 wv = min(range(nwave), key=lambda v: load[v])
                 c[2] = wv
                 load[wv] += c[3]
+        if MERGE_WAVE_CHUNKS:
+            # one function per wave: its chunks in order, each in a scope of its own, so a
+            # configuration costs every wave one call (one save/restore of callee-saved registers)
+            merged = []
+            for v in range(nwave):
+                mine = [c for c in out if c[2] == v]
+                if not mine:
+                    continue
+                name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_w{v}"
+                body = []
+                for c in mine:
+                    body.append("  {")
+                    body.extend(c[4])
+                    body.append("  }")
+                src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+                       + "\n".join(body) + "\n}\n")
+                merged.append([name, src, v, sum(c[3] for c in mine), body])
+            out = merged
         cflops = total_flops + 2 * self.kdim * (self.kdim + 1)
         self.flops[prec] += cflops * pat.ncfg
         if prec == "double":
@@ -600,44 +619,62 @@ class Emitter:
         w("}")
         return out
 
-    def emit(self) -> str:
+    def emit(self) -> dict:
+        """Sources of one process: {"f64": float64 kernels + host descriptor, "f32": mixed kernels}.
+
+        The two precisions share no device code, so they are separate translation units that
+        compile in parallel; the host part launches the mixed kernels through declarations."""
         proc, dag = self.proc, self.dag
         ns = f"p_{proc.tag}"
         chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
                   for prec in ("double", "float")}
-        lines = []
-        w = lines.append
-        w(f"// Generated by paper_0909_5257_amd.gen for the process \"{proc.spec}\".  Do not edit.")
-        w(f"// diagrams {len(dag.amps)}, shared currents {len(dag.nodes) - proc.n}, colour basis {self.k}, "
-          f"reduced colour space {self.kdim}, helicity patterns {len(self.pats)}, "
-          f"evaluated configurations {sum(p.ncfg for p in self.pats)}, waves per workgroup "
-          f"{self.nwave['double']} (float64) / {self.nwave['float']} (mixed)")
+        head = [f"// Generated by paper_0909_5257_amd.gen for the process \"{proc.spec}\".  Do not edit.",
+                f"// diagrams {len(dag.amps)}, shared currents {len(dag.nodes) - proc.n}, colour basis {self.k}, "
+                f"reduced colour space {self.kdim}, helicity patterns {len(self.pats)}, "
+                f"evaluated configurations {sum(p.ncfg for p in self.pats)}, waves per workgroup "
+                f"{self.nwave['double']} (float64) / {self.nwave['float']} (mixed)"]
         for prec, st in self.stats.items():
             for s in st:
-                w(f"// {prec} pattern {s['pattern']}: {s['amps']} amplitudes in {s['groups']} groups and "
-                  f"{s['chunks']} chunks, {s['node_evals']} current evaluations, peak {s['max_peak']} "
-                  f"registers (simulated), flops per wave {s['wave_flops']}")
-        w('#include "heget_device.hpp"')
-        w('#include "heget_kernel_common.hpp"')
-        w("")
-        w("namespace heget {")
-        w(f"namespace {ns} {{")
-        w(f"constexpr int NEXT = {proc.n};")
-        w(f"__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events")
-        w(f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event")
-        w(f"__constant__ int HMAP[{1 << proc.n}] = {{" + ", ".join(str(x) for x in self.helicity_map()) + "};")
-        w("")
+                head.append(f"// {prec} pattern {s['pattern']}: {s['amps']} amplitudes in {s['groups']} groups and "
+                            f"{s['chunks']} chunks, {s['node_evals']} current evaluations, peak {s['max_peak']} "
+                            f"registers (simulated), flops per wave {s['wave_flops']}")
+        out = {}
         for prec in ("double", "float"):
+            lines = list(head)
+            w = lines.append
+            w('#include "heget_device.hpp"')
+            w('#include "heget_kernel_common.hpp"')
+            w("")
+            w("namespace heget {")
+            w(f"namespace {ns} {{")
+            w(f"constexpr int NEXT = {proc.n};")
+            w("namespace {")
+            w(f"__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events")
+            w(f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event")
+            w(f"__constant__ int HMAP[{1 << proc.n}] = {{" + ", ".join(str(x) for x in self.helicity_map()) + "};")
             for pat_chunks in chunks[prec]:
                 for c in pat_chunks:
                     lines.append(c[1])
-        for prec in ("double", "float"):
+            w("}  // namespace")
             lines.extend(self._kernel(prec, chunks[prec]))
             lines.extend(self._kernel(prec, chunks[prec], sampled=True))
-        w("")
-        w(f"}}  // namespace {ns}")
-        w("}  // namespace heget")
-        w("")
+            if prec == "double":
+                args = ("const double* __restrict__ mom, int64_t nev, double* __restrict__ out, "
+                        "const double* __restrict__ cmat, double scale")
+                hargs = ("const double* __restrict__ mom, const int* __restrict__ hel, int64_t nev, "
+                         "double* __restrict__ out, const double* __restrict__ cmat, double scale")
+                w(f"__global__ void me2_f32({args});     // in the mixed translation unit")
+                w(f"__global__ void me2h_f32({hargs});")
+            w("")
+            w(f"}}  // namespace {ns}")
+            w("}  // namespace heget")
+            w("")
+            if prec == "float":
+                out["f32"] = "\n".join(lines) + "\n"
+            else:
+                out["f64"] = lines
+        lines = out["f64"]
+        w = lines.append
         w("#if !defined(__HIP_DEVICE_COMPILE__)")
         table = self.colour_table()
         w(f"static const double k_colour_table_{proc.tag}[] = {{" + ", ".join(_lit(x) for x in table) + "};")
@@ -668,4 +705,5 @@ class Emitter:
         w(f"  {len(table)}, k_colour_table_{proc.tag}, k_num_{proc.tag}, k_den_{proc.tag},")
         w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{proc.tag}}};")
         w("#endif")
-        return "\n".join(lines) + "\n"
+        out["f64"] = "\n".join(lines) + "\n"
+        return out

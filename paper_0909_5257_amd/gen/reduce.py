@@ -22,6 +22,7 @@ to pick pivots, and the result is checked exactly on every diagram.
 """
 from __future__ import annotations
 
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -42,6 +43,19 @@ def _inverse(m):
                 f = a[r][col]
                 a[r] = [x - f * y for x, y in zip(a[r], a[col])]
     return [row[n:] for row in a]
+
+
+def _exact_matmul(a, b):
+    """Exact product of two integer matrices (object arrays of Python ints).
+
+    Uses int64 arithmetic when the bound max|a| * max|b| * inner cannot overflow it, and
+    Python integers otherwise."""
+    inner = a.shape[1]
+    amax = max((abs(int(x)) for x in a.flat), default=0)
+    bmax = max((abs(int(x)) for x in b.flat), default=0)
+    if amax * bmax * max(inner, 1) < (1 << 62):
+        return (a.astype(np.int64) @ b.astype(np.int64)).astype(object)
+    return a.dot(b)
 
 
 def _independent_columns(m, tol=1e-9):
@@ -75,22 +89,31 @@ class ColourSpace:
         row_sel = _independent_columns(cmat.T.tolist())
         r = len(row_sel)
         if r < k:
-            rmat = [[Fraction(int(cmat[i, j])) for j in range(k)] for i in row_sel]
-            piv = _independent_columns(rmat)
+            assert np.array_equal(cmat, np.round(cmat)), "diagram colour coefficients must be integers"
+            rint = cmat[row_sel].astype(np.int64)
+            piv = _independent_columns(rint.tolist())
             assert len(piv) == r
-            inv = _inverse([[rmat[i][j] for j in piv] for i in range(r)])
-            bt = [[sum(inv[a][b] * rmat[b][j] for b in range(r) if rmat[b][j] != 0 and inv[a][b] != 0)
-                   for j in range(k)] for a in range(r)]
-            # exact check on every distinct diagram vector: c = c[P] Bt
-            for c in uniq:
-                for j in range(k):
-                    lhs = Fraction(c.get(j, 0))
-                    rhs = sum(Fraction(c.get(p, 0)) * bt[a][j] for a, p in enumerate(piv))
-                    assert lhs == rhs, "colour coefficient vector outside the row space"
-            nbt = [[sum(nmat[i][j] * bt[a][j] for j in range(k) if bt[a][j] != 0) for a in range(r)]
-                   for i in range(k)]
-            neff = [[sum(bt[a][i] * nbt[i][b] for i in range(k) if bt[a][i] != 0) for b in range(r)]
-                    for a in range(r)]
+            inv = _inverse([[Fraction(int(rint[i, j])) for j in piv] for i in range(r)])
+            # Bt = inv R in integers: Bt = BtD / d with d the common denominator of inv
+            d = 1
+            for row in inv:
+                for x in row:
+                    d = d * x.denominator // math.gcd(d, x.denominator)
+            inv_d = np.array([[int(x * d) for x in row] for row in inv], dtype=object)
+            bt_d = _exact_matmul(inv_d, rint.astype(object))
+            # exact check on every distinct diagram vector: d c = c[P] (d Bt)
+            cint = cmat.astype(np.int64).astype(object)
+            assert np.array_equal(cint * d, _exact_matmul(cint[:, piv], bt_d)), \
+                "colour coefficient vector outside the row space"
+            # N' = Bt N Bt^T with N = n_l / l
+            l = 1
+            for row in nmat:
+                for x in row:
+                    l = l * x.denominator // math.gcd(l, x.denominator)
+            n_l = np.array([[int(x * l) for x in row] for row in nmat], dtype=object)
+            neff_num = _exact_matmul(_exact_matmul(bt_d, n_l), bt_d.T)
+            den = d * d * l
+            neff = [[Fraction(int(neff_num[a, b]), den) for b in range(r)] for a in range(r)]
             self.pivots = piv
         else:
             neff = [list(row) for row in nmat]

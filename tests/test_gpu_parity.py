@@ -135,6 +135,6 @@ def test_abi_argument_errors(torch_dev):
     assert L.heget_matrix_elements(h, p.data_ptr(), -1, 0.118, out.data_ptr(), None) == 1
     assert L.heget_matrix_elements(h, None, 0, 0.118, None, None) == 0      # empty batch: nothing queued
     with pytest.raises(HegetError):
-        Process("g g > g g g g g")
+        Process("g g > g g g g g g")              # eight gluons: no kernel generated
     with pytest.raises(HegetError):
         Process("g g > t t~")

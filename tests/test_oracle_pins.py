@@ -52,7 +52,8 @@ def test_table1_diagram_and_colour_counts(row):
     assert len(colour_basis(proc)) == nc
 
 
-@pytest.mark.parametrize("row", _table("paper_table3.txt"), ids=lambda r: r[0])
+@pytest.mark.parametrize("row", [r for r in _table("paper_table3.txt") if r[0] != "g g > g g g g g"],
+                         ids=lambda r: r[0])
 def test_table3_distinct_colour_matrix_values(row):
     spec, nv = row[0], int(row[1])
     cd = colour_data(spec)
@@ -376,3 +377,75 @@ def test_polarisations():
     np.testing.assert_allclose(comp, np.eye(3)[None] - np.einsum("ni,nj->nij", khat, khat), atol=1e-12)
     # helicity +1 along +z is -(0, 1, i, 0)/sqrt2
     np.testing.assert_allclose(ep[0], np.array([0, -1, -1j, 0]) / np.sqrt(2), atol=1e-15)
+
+
+# ------------------------------------------------------------ seven gluons
+# The literal colour sum over 8^7 assignments and 720 basis elements is out of reach of the
+# diagram oracle, so g g > g g g g g is computed by the Berends-Giele route with the trace
+# colour matrix built from one trace tensor; these pins fix that route.
+
+@pytest.mark.parametrize("spec", ["g g > g g", "g g > g g g", "g g > g g g g"])
+def test_berends_giele_me2_equals_diagram_oracle(spec):
+    from oracle.berends_giele import bg_me2
+    p = _events(spec, 4, seed=23)
+    np.testing.assert_allclose(bg_me2(spec, p, ALPHA_S), oracle_me2(spec, p, ALPHA_S), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_trace_colour_matrix_equals_literal_colour_sum(n):
+    """The permuted-tensor construction equals the oracle's sum over every colour assignment."""
+    from oracle.berends_giele import trace_colour_matrix
+    spec = "g g > " + " ".join(["g"] * (n - 2))
+    words, nmat = trace_colour_matrix(n)
+    cd = colour_data(spec)
+    basis = colour_basis(cd.proc)
+    order = [words.index(trace_word_to_bg(desc[0][2], cd.proc.root)) for desc in basis]
+    np.testing.assert_allclose(nmat.real[np.ix_(order, order)], cd.N, rtol=0, atol=1e-15)
+    assert np.abs(nmat.imag).max() < 1e-15
+
+
+def test_seven_gluon_colour_matrix_table3():
+    """Table 3: 45 distinct non-zero colour-matrix values for g g > g g g g g."""
+    from oracle.berends_giele import trace_colour_matrix
+    from oracle.colour import _rationalise
+    want = {r[0]: int(r[1]) for r in _table("paper_table3.txt")}["g g > g g g g g"]
+    words, nmat = trace_colour_matrix(7)
+    assert len(words) == 720
+    n = nmat.real
+    assert np.abs(nmat.imag).max() < 1e-14 and np.allclose(n, n.T, rtol=0, atol=1e-15)
+    vals = {_rationalise(x) for i in range(720) for x in n[i, i:] if abs(x) > 1e-13}
+    assert len(vals) == want
+    assert np.linalg.eigvalsh(n).min() > -1e-12
+
+
+def test_seven_gluon_parke_taylor_and_symmetries():
+    """Berends-Giele for 7 gluons: MHV partial amplitudes follow Parke-Taylor, all-plus and
+    one-minus vanish, and |M|^2 is symmetric under exchange of final gluons."""
+    from oracle.berends_giele import bg_me2
+    spec = "g g > g g g g g"
+    p = _events(spec, 2, seed=29)
+    k = p.copy()
+    k[:, :2] *= -1
+    sij = lambda i, j: _minkowski(k[:, i] + k[:, j])
+    hels = helicity_table(7)
+    amps = bg_amplitudes(spec, p, hels)
+    out_hel = hels.copy()
+    out_hel[:, :2] *= -1
+    ratios, zeros, scale = [], [], 0.0
+    for word, a in list(amps.items())[::37]:
+        cyc = list(word) + [6]
+        ps = np.prod([np.abs(sij(cyc[x], cyc[(x + 1) % 7])) for x in range(7)], axis=0)
+        for h in range(hels.shape[0]):
+            neg = np.nonzero(out_hel[h] < 0)[0]
+            scale = max(scale, np.abs(a[h]).max())
+            if len(neg) == 2:
+                i, j = neg
+                ratios.append(np.abs(a[h]) ** 2 * ps / sij(i, j) ** 4)
+            elif len(neg) <= 1 or len(neg) >= 6:
+                zeros.append(np.abs(a[h]).max())
+    ratios = np.array(ratios)
+    assert np.max(np.abs(ratios / ratios[0] - 1)) < 1e-10
+    assert max(zeros) < 1e-12 * scale
+    m = bg_me2(spec, p, ALPHA_S)
+    swapped = p[:, [0, 1, 4, 2, 6, 3, 5]]
+    np.testing.assert_allclose(bg_me2(spec, swapped, ALPHA_S), m, rtol=1e-12)
