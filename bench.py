@@ -31,6 +31,36 @@ PEAK_ALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz: FP64,
 WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 
 
+# HBM traffic per event of the benchmark's kernels: rocprofv3 FETCH_SIZE (x 2) plus WRITE_SIZE (x 1),
+# both scaled by what the same counters read for a plain device copy of known size in the same run,
+# at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
+# digest of the kernel's generated source: a kernel that has changed since reports null.
+MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
+    ("u u~ > g g g g g", "fp64"): ("975b61b611c46bf6", 407203),
+    ("u u~ > g g g g g", "mixed"): ("25c8767794fd639e", 848160),
+    ("g g > g g g g", "fp64"): ("9e4a242819ccc89f", 42973),
+    ("g g > g g g g", "mixed"): ("781da62bf5002d35", 168664),
+}
+
+
+def kernel_digest(spec: str, precision: str):
+    import hashlib
+    from paper_0909_5257_amd.gen.model import parse
+    path = os.path.join(ROOT, "paper_0909_5257_amd", "csrc", "generated",
+                        f"proc_{parse(spec).tag}_{'f64' if precision == 'fp64' else 'f32'}.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(spec: str, precision: str, n_events: int):
+    rec = MEASURED_TRAFFIC.get((spec, precision))
+    if rec is None or rec[0] != kernel_digest(spec, precision):
+        return None
+    return rec[1] * n_events
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -333,7 +363,8 @@ def main():
             "roofline": {"bound": "alu", "kernel": f"me2_kernel<{'double' if precision == 'fp64' else 'float'}> "
                                                    f"({spec})",
                          "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None},
+                         "frac": achieved / PEAK_ALU_TFLOPS, "traffic": measured_traffic(spec, precision, n),
+                         "algorithmic_bytes": (32 * int(dev_inputs[dom].shape[1]) + 8) * n},
         }
 
     cpu = None

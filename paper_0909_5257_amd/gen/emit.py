@@ -46,8 +46,13 @@ LDS_PER_CU = 160 * 1024   # bytes of LDS per compute unit (gfx950)
 # excess in AGPRs instead of scratch), so one wave per SIMD with the whole register file.
 TARGET_WAVES_PER_CU = {"double": 4, "float": 8}
 FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process and precision (for tuning)
-INLINE_CHUNKS = False     # inline the chunk functions into the kernel instead of calling them
-MERGE_WAVE_CHUNKS = False  # one called function per wave holding all of that wave's chunks
+# Each call of a chunk function saves and restores the callee-saved registers it uses (scratch
+# traffic), so a wave's consecutive chunks are merged into one called function of up to this many
+# chunks.  Merged functions compile more slowly; patterns with more than MERGE_MAX_PATTERN_CHUNKS
+# chunks (g g > g g g g g) keep one function per chunk so that no translation unit takes much
+# longer than a quarter of an hour.
+MERGE_WAVE_CHUNKS = 8
+MERGE_MAX_PATTERN_CHUNKS = 64
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 
 SIZES = {   # 32-bit registers per value
@@ -430,8 +435,7 @@ class Emitter:
                         else:
                             w(f"  yl[{a}][0][lane] += {_lit(sc)} * k{ci}.re; yl[{a}][1][lane] += {_lit(sc)} * k{ci}.im;")
             name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_c{ki}"
-            qual = "__attribute__((always_inline)) inline" if INLINE_CHUNKS else "__noinline__"
-            src = (f"__device__ {qual} void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+            src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
                    + "\n".join(lines) + "\n}\n")
             out.append([name, src, 0, flops, lines])
             total_flops += flops
@@ -443,23 +447,23 @@ class Emitter:
                 wv = min(range(nwave), key=lambda v: load[v])
                 c[2] = wv
                 load[wv] += c[3]
-        if MERGE_WAVE_CHUNKS:
-            # one function per wave: its chunks in order, each in a scope of its own, so a
-            # configuration costs every wave one call (one save/restore of callee-saved registers)
+        if MERGE_WAVE_CHUNKS > 1 and len(out) <= MERGE_MAX_PATTERN_CHUNKS:
+            # a wave's chunks in order, each in a scope of its own, merged into functions of up to
+            # MERGE_WAVE_CHUNKS chunks: fewer calls, fewer saves of callee-saved registers
             merged = []
             for v in range(nwave):
                 mine = [c for c in out if c[2] == v]
-                if not mine:
-                    continue
-                name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_w{v}"
-                body = []
-                for c in mine:
-                    body.append("  {")
-                    body.extend(c[4])
-                    body.append("  }")
-                src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
-                       + "\n".join(body) + "\n}\n")
-                merged.append([name, src, v, sum(c[3] for c in mine), body])
+                for m0 in range(0, len(mine), MERGE_WAVE_CHUNKS):
+                    run = mine[m0:m0 + MERGE_WAVE_CHUNKS]
+                    name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_w{v}_{m0 // MERGE_WAVE_CHUNKS}"
+                    body = []
+                    for c in run:
+                        body.append("  {")
+                        body.extend(c[4])
+                        body.append("  }")
+                    src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+                           + "\n".join(body) + "\n}\n")
+                    merged.append([name, src, v, sum(c[3] for c in run), body])
             out = merged
         cflops = total_flops + 2 * self.kdim * (self.kdim + 1)
         self.flops[prec] += cflops * pat.ncfg
