@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("975b61b611c46bf6", 407203),
-    ("u u~ > g g g g g", "mixed"): ("25c8767794fd639e", 848160),
-    ("g g > g g g g", "fp64"): ("9e4a242819ccc89f", 42973),
-    ("g g > g g g g", "mixed"): ("781da62bf5002d35", 168664),
+    ("u u~ > g g g g g", "fp64"): ("975b61b611c46bf6", 406973),
+    ("g g > g g g g", "fp64"): ("205b14bfea873bf9", 132736),
+    ("u u~ > g g g g g", "mixed"): ("25c8767794fd639e", 842465),
+    ("g g > g g g g", "mixed"): ("698e91162e8b34eb", 168703),
 }
 
 

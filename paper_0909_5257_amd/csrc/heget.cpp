@@ -1,5 +1,6 @@
 // C ABI of the matrix-element library: process lookup, device state, launches.
 #include "heget.h"
+#include "heget_internal.hpp"
 
 #include <hip/hip_runtime.h>
 

@@ -18,8 +18,7 @@
 #include <cmath>
 
 #include "heget.h"
-
-double heget_detail_final_symmetry(heget_process_t p);   // defined with the process registry
+#include "heget_internal.hpp"
 
 namespace {
 

@@ -54,6 +54,13 @@ FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process a
 MERGE_WAVE_CHUNKS = 8
 MERGE_MAX_PATTERN_CHUNKS = 64
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
+# Per (process, precision) choices that measured faster on MI355X than the defaults above:
+# "externals": "group" rebuilds each external wavefunction inside every group from the LDS
+# momenta (nothing stays live across groups, so a larger budget fits); the default keeps the
+# chunk's external momenta and wavefunctions in registers across its groups.
+TUNED = {
+    ("g g > g g g g", "double"): {"externals": "group", "budget": 256},
+}
 
 SIZES = {   # 32-bit registers per value
     "double": {"V": 16, "I": 8, "O": 8, "P": 8, "Q": 0, "inv": 2, "amp": 4, "pl": 8},
@@ -188,9 +195,15 @@ class _Group:
         return f"g{self.gid}_{key[0]}{'_'.join(str(x) for x in key[1:])}"
 
     def leg_mom(self, leg):
+        """The leg's momentum: an opaque copy of the chunk's value, or read from LDS in the group."""
         key = ("pl", leg)
         if key not in self.defs:
-            self.lines.append(f"  const mom4<double> {self.name(key)} = fresh(pl{leg});")
+            if self.em.group_externals[self.prec]:
+                src = (f"mom4<double>{{pml[{leg}][0][lane], pml[{leg}][1][lane], pml[{leg}][2][lane], "
+                       f"pml[{leg}][3][lane]}}")
+            else:
+                src = f"pl{leg}"
+            self.lines.append(f"  const mom4<double> {self.name(key)} = fresh({src});")
             self._def(key, SIZES[self.prec]["pl"])
         self._use(key)
         return self.name(key)
@@ -243,10 +256,28 @@ class _Group:
         h = self.pat.hq
         args = [self.node(a) for a in nd.args]
         op = nd.op
-        if op == "ext":
+        if op == "ext" and not em.group_externals[self.prec]:
             leg = em.proc.legs[nd.leg]
             typ = "vec4<R>" if leg.kind == "V" else "wsp<R>"
             expr = f"fresh(w{leg.index})"
+        elif op == "ext":
+            # external wavefunction rebuilt in the group from the LDS momentum
+            leg = em.proc.legs[nd.leg]
+            pl = self.leg_mom(leg.index)
+            if leg.kind == "V":
+                typ = "vec4<R>"
+                if leg.index in self.pat.fixed:
+                    lam = str(self.pat.fixed[leg.index])
+                else:
+                    lam = f"((cfg >> {self.pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
+                expr = f"vxxxx0<R>({pl}, {lam}, {'false' if leg.incoming else 'true'})"
+            elif leg.kind == "I":
+                typ = "wsp<R>"
+                expr = f"ixxxx0<R, {h[leg.index]}>({pl})"
+            else:
+                typ = "wsp<R>"
+                expr = f"oxxxx0<R, {h[leg.index]}>({pl})"
+            self.flops += FLOPS["ext"]
         elif op == "jvv":
             x, y = nd.args
             typ = "vec4<R>"
@@ -319,6 +350,9 @@ class Emitter:
         self.kdim = self.cs.dim
         self.vectors = {i: self.cs.vector(a.coef) for i, a in enumerate(dag.amps)}
         self.pats = patterns(dag)
+        tuned = {prec: TUNED.get((self.proc.spec, prec), {}) for prec in ("double", "float")}
+        self.group_externals = {prec: tuned[prec].get("externals") == "group" for prec in tuned}
+        self.budget = {prec: tuned[prec].get("budget", GROUP_BUDGET[prec]) for prec in tuned}
         self.nwave = {prec: self.waves_per_workgroup(prec) for prec in ("double", "float")}
         # colour-sum row blocks: the largest block size that still gives every wave two blocks
         most = max(self.nwave.values())
@@ -352,7 +386,7 @@ class Emitter:
         classes = colour_classes(self.vectors, pat.amps)
         items = [(ci, ai, fac) for ci, (_, members) in enumerate(classes) for ai, fac in members]
         groups, cur = [], []
-        budget = GROUP_BUDGET[prec]
+        budget = self.budget[prec]
         g = _Group(self, pat, prec, 0)
         for it in items:
             g.amplitude(it[1], "acc", it[2])
@@ -397,32 +431,36 @@ class Emitter:
         h = pat.hq
         prologue = []
         w = prologue.append
-        for leg in proc.legs:
-            w(f"  const mom4<double> pl{leg.index}{{pml[{leg.index}][0][lane], pml[{leg.index}][1][lane], "
-              f"pml[{leg.index}][2][lane], pml[{leg.index}][3][lane]}};")
-        for leg in proc.legs:
-            if leg.kind == "V":
-                if leg.index in pat.fixed:
-                    lam = str(pat.fixed[leg.index])
+        if not self.group_externals[prec]:
+            for leg in proc.legs:
+                w(f"  const mom4<double> pl{leg.index}{{pml[{leg.index}][0][lane], pml[{leg.index}][1][lane], "
+                  f"pml[{leg.index}][2][lane], pml[{leg.index}][3][lane]}};")
+            for leg in proc.legs:
+                if leg.kind == "V":
+                    if leg.index in pat.fixed:
+                        lam = str(pat.fixed[leg.index])
+                    else:
+                        lam = f"((cfg >> {pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
+                    w(f"  const vec4<R> w{leg.index} = vxxxx0<R>(pl{leg.index}, {lam}, "
+                      f"{'false' if leg.incoming else 'true'});")
+                elif leg.kind == "I":
+                    w(f"  const wsp<R> w{leg.index} = ixxxx0<R, {h[leg.index]}>(pl{leg.index});")
                 else:
-                    lam = f"((cfg >> {pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
-                w(f"  const vec4<R> w{leg.index} = vxxxx0<R>(pl{leg.index}, {lam}, "
-                  f"{'false' if leg.incoming else 'true'});")
-            elif leg.kind == "I":
-                w(f"  const wsp<R> w{leg.index} = ixxxx0<R, {h[leg.index]}>(pl{leg.index});")
-            else:
-                w(f"  const wsp<R> w{leg.index} = oxxxx0<R, {h[leg.index]}>(pl{leg.index});")
+                    w(f"  const wsp<R> w{leg.index} = oxxxx0<R, {h[leg.index]}>(pl{leg.index});")
         out = []
         total_flops = 0
         for ki, gis in enumerate(chunks):
             lines = list(prologue)
             w = lines.append
-            flops = FLOPS["ext"] * proc.n
+            flops = 0 if self.group_externals[prec] else FLOPS["ext"] * proc.n
             for gi in gis:
                 items = groups[gi]
                 for ci in sorted({c for c, _, _ in items if min(g for g in range(len(groups))
                                                                  if any(x == c for x, _, _ in groups[g])) == gi}):
                     w(f"  cx<double> k{ci}{{0.0, 0.0}};")
+                if self.group_externals[prec]:
+                    # a group starts from LDS: no load is reused from an earlier group
+                    w('  asm volatile("" ::: "memory");')
                 w("  __builtin_amdgcn_sched_barrier(0);")
                 lines.extend(built[gi].lines)
                 flops += built[gi].flops
