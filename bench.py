@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("975b61b611c46bf6", 406973),
-    ("g g > g g g g", "fp64"): ("205b14bfea873bf9", 132736),
-    ("u u~ > g g g g g", "mixed"): ("25c8767794fd639e", 842465),
-    ("g g > g g g g", "mixed"): ("698e91162e8b34eb", 168703),
+    ("u u~ > g g g g g", "fp64"): ("1f7b0e65ead11695", 406974),
+    ("g g > g g g g", "fp64"): ("789094078d751f3b", 132738),
+    ("u u~ > g g g g g", "mixed"): ("714c749c5931e64b", 852093),
+    ("g g > g g g g", "mixed"): ("0861d2f519c7e7d3", 65920),
 }
 
 
@@ -218,10 +218,14 @@ def _timed(torch, fn, steps, warmup):
 
 def helicity_mc_run(torch, workload, dev_inputs, steps, warmup):
     """One drawn helicity configuration per event (the paper's per-event workload, section 3.2)."""
-    from phasespace import random_helicities
+    from phasespace import KIN_C2, generate_events, random_helicities
     from paper_0909_5257_amd.heget import Process
     out = {}
-    for (spec, n, stream), x in zip(workload, dev_inputs):
+    # plus a two-quark-line process, whose events the library sorts by chirality pattern; its
+    # summed path is timed too, for the ratio of the two
+    extra = ("u u > u u g g g", workload[0][1] >> 2, 2)
+    extra_x = torch.from_numpy(generate_events(extra[1], 5, KIN_C2, seed=0, stream=extra[2])).to("cuda")
+    for (spec, n, stream), x in list(zip(workload, dev_inputs)) + [(extra, extra_x)]:
         hel = torch.from_numpy(random_helicities(n, x.shape[1], seed=0, stream=stream)).to("cuda")
         res = torch.empty(n, dtype=torch.float64, device="cuda")
         row = {}
@@ -229,6 +233,9 @@ def helicity_mc_run(torch, workload, dev_inputs, steps, warmup):
             pr = Process(spec, precision)
             ms = _timed(torch, lambda: pr.matrix_elements_helicity(x, hel, ALPHA_S, out=res), steps, warmup)
             row[precision] = {"ms_per_launch": ms, "events_per_s": n / (ms * 1e-3)}
+            if spec == extra[0]:
+                ms_sum = _timed(torch, lambda: pr.matrix_elements(x, ALPHA_S, out=res), steps, warmup)
+                row[precision]["summed_events_per_s"] = n / (ms_sum * 1e-3)
         out[spec] = {"events": n, **row}
         log(f"[bench] helicity MC {spec}: fp64 {row['fp64']['events_per_s']:.3e}, "
             f"mixed {row['mixed']['events_per_s']:.3e} events/s")

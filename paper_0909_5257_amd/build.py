@@ -57,6 +57,15 @@ for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS", "TARGET_WAVES_PER_CU", "FORCE_W
             setattr(_emit, _name, {"double": _d, "float": _f})
         else:
             setattr(_emit, _name, int(_val))
+if os.environ.get("HEGET_TUNED_JSON"):
+    # planner settings per "process|double|float" key, from the tuner; HEGET_TUNED_REPLACE=1 drops
+    # the committed table first (so that the tuner's default candidate really is the default)
+    import json as _json
+    from .gen import emit as _emit
+    _extra = {tuple(k.split("|")): v for k, v in _json.loads(os.environ["HEGET_TUNED_JSON"]).items()}
+    if os.environ.get("HEGET_TUNED_REPLACE") == "1":
+        _emit.TUNED = {}
+    _emit.TUNED.update(_extra)
 for _prec in ("double", "float"):
     _env = os.environ.get(f"HEGET_GROUP_BUDGET_{'F64' if _prec == 'double' else 'F32'}")
     if _env:

@@ -3,6 +3,7 @@
 #include "heget_internal.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -25,6 +26,7 @@ struct heget_process {
   int precision;
   int device;
   double* colour_table_dev;
+  int* pattern_dev;      // helicity bit pattern -> chirality pattern (processes with several)
 };
 
 namespace {
@@ -37,6 +39,19 @@ std::string normalise(const char* spec) {
     out += tok;
   }
   return out;
+}
+
+// Sort key of each event of the sampled-helicity mode: its chirality pattern, or n_patterns for a
+// structural zero or an out-of-range pattern (those do no work and are sorted last).
+__global__ void pattern_keys(const int32_t* __restrict__ hel, int n, int n_ext, const int* __restrict__ table,
+                             int n_patterns, int* __restrict__ keys, int* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int h = hel[i];
+  int k = n_patterns;
+  if (h >= 0 && h < (1 << n_ext) && table[h] >= 0) k = table[h];
+  keys[i] = k;
+  idx[i] = i;
 }
 
 const heget_proc_desc* find(const std::string& spec) {
@@ -55,7 +70,7 @@ heget_status heget_create_process(const char* spec, heget_precision precision, h
   if (precision != HEGET_FP64 && precision != HEGET_MIXED) return HEGET_E_INVALID_ARG;
   const heget_proc_desc* d = find(normalise(spec));
   if (!d) return HEGET_E_UNSUPPORTED_PROCESS;
-  heget_process* p = new (std::nothrow) heget_process{d, (int)precision, 0, nullptr};
+  heget_process* p = new (std::nothrow) heget_process{d, (int)precision, 0, nullptr, nullptr};
   if (!p) return HEGET_E_OUT_OF_MEMORY;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -70,6 +85,17 @@ heget_status heget_create_process(const char* spec, heget_precision precision, h
     if (hipMemcpy(p->colour_table_dev, d->colour_table, bytes, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(p->colour_table_dev);
       delete p;
+      return HEGET_E_DEVICE;
+    }
+  }
+  if (d->n_patterns > 1) {
+    const size_t bytes = sizeof(int) * ((size_t)1 << d->n_ext);
+    if (hipMalloc(&p->pattern_dev, bytes) != hipSuccess) {
+      heget_destroy_process(p);
+      return HEGET_E_OUT_OF_MEMORY;
+    }
+    if (hipMemcpy(p->pattern_dev, d->helicity_pattern, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      heget_destroy_process(p);
       return HEGET_E_DEVICE;
     }
   }
@@ -101,8 +127,8 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
   // 2: configurations with leg 0 at helicity -1 equal their all-flipped partners;
   // 1/4: initial spin average; g^(2(n-2)): couplings left out of the kernels.
   const double scale = 2.0 * 0.25 * std::pow(g2, p->desc->n_ext - 2);
-  hipError_t e = p->desc->launch(p->precision, momenta, nullptr, n_events, me2, p->colour_table_dev, scale,
-                                 reinterpret_cast<hipStream_t>(stream));
+  hipError_t e = p->desc->launch(p->precision, momenta, nullptr, nullptr, n_events, me2, p->colour_table_dev,
+                                 scale, reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
 }
 
@@ -120,9 +146,41 @@ heget_status heget_matrix_elements_helicity(heget_process_t p, const double* mom
   const double g2 = 4.0 * M_PI * alpha_s;
   // one term of the helicity sum: 1/4 initial spin average and the couplings, no flip factor
   const double scale = 0.25 * std::pow(g2, p->desc->n_ext - 2);
-  hipError_t e = p->desc->launch(p->precision, momenta, helicity, n_events, me2, p->colour_table_dev, scale,
-                                 reinterpret_cast<hipStream_t>(stream));
-  return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (p->pattern_dev == nullptr || n_events >= (int64_t(1) << 31)) {
+    hipError_t e = p->desc->launch(p->precision, momenta, helicity, nullptr, n_events, me2, p->colour_table_dev,
+                                   scale, s);
+    return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+  }
+  // several chirality patterns: order the events by pattern (stable radix sort of the pattern
+  // keys) so that a workgroup's 64 events share one pattern and run one pass instead of all
+  const int n = (int)n_events;
+  int *keys = nullptr, *keys_out = nullptr, *idx = nullptr, *perm = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  int bits = 1;
+  while ((1 << bits) <= p->desc->n_patterns) ++bits;
+  heget_status st = HEGET_OK;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys, keys_out, idx, perm, n, 0, bits, s) !=
+      hipSuccess)
+    return HEGET_E_DEVICE;
+  const size_t nb = sizeof(int) * (size_t)n;
+  if (hipMallocAsync(&keys, nb, s) != hipSuccess || hipMallocAsync(&keys_out, nb, s) != hipSuccess ||
+      hipMallocAsync(&idx, nb, s) != hipSuccess || hipMallocAsync(&perm, nb, s) != hipSuccess ||
+      hipMallocAsync(&temp, temp_bytes, s) != hipSuccess) {
+    st = HEGET_E_OUT_OF_MEMORY;
+  } else {
+    hipLaunchKernelGGL(pattern_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, helicity, n,
+                       p->desc->n_ext, p->pattern_dev, p->desc->n_patterns, keys, idx);
+    if (hipGetLastError() != hipSuccess ||
+        hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_out, idx, perm, n, 0, bits, s) != hipSuccess ||
+        p->desc->launch(p->precision, momenta, helicity, perm, n_events, me2, p->colour_table_dev, scale, s) !=
+            hipSuccess)
+      st = HEGET_E_DEVICE;
+  }
+  for (void* b : {(void*)keys, (void*)keys_out, (void*)idx, (void*)perm, temp})
+    if (b) (void)hipFreeAsync(b, s);
+  return st;
 }
 
 }  // extern "C"
@@ -196,7 +254,8 @@ hipError_t enqueue_batch(DevicePool* pool, const heget_batch_item* items, int n,
     load[s] += cost(i);
     used[s] = true;
     const heget_process* p = items[i].process;
-    e = p->desc->launch(p->precision, items[i].momenta, nullptr, items[i].n_events, items[i].me2, p->colour_table_dev,
+    e = p->desc->launch(p->precision, items[i].momenta, nullptr, nullptr, items[i].n_events, items[i].me2,
+                        p->colour_table_dev,
                         item_scale(p->desc, alpha_s), pool->streams[s]);
     if (e != hipSuccess) return e;
   }
@@ -297,6 +356,7 @@ heget_status heget_process_flops(heget_process_t p, int64_t* flops_per_event) {
 void heget_destroy_process(heget_process_t p) {
   if (!p) return;
   if (p->colour_table_dev) (void)hipFree(p->colour_table_dev);
+  if (p->pattern_dev) (void)hipFree(p->pattern_dev);
   delete p;
 }
 

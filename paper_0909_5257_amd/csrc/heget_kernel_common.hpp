@@ -20,9 +20,12 @@ struct heget_proc_desc {
   const long long* colour_den;
   long long flops_per_event[2];  // floating-point operations one event executes (float64, mixed), incl. recomputation
   long long algo_flops_per_event;  // the same with every shared current counted once (roofline numerator)
-  // hel == nullptr: sum over helicities; otherwise one helicity bit pattern per event
-  hipError_t (*launch)(int precision, const double* mom, const int* hel, int64_t n, double* out,
-                       const double* colour_table_dev, double scale, hipStream_t stream);
+  // hel == nullptr: sum over helicities; otherwise one helicity bit pattern per event, and with
+  // perm != nullptr launch slot i evaluates event perm[i]
+  hipError_t (*launch)(int precision, const double* mom, const int* hel, const int* perm, int64_t n,
+                       double* out, const double* colour_table_dev, double scale, hipStream_t stream);
+  int n_patterns;                // quark-chirality patterns of the sampled-helicity kernels
+  const int* helicity_pattern;   // per bit pattern h: its chirality pattern, -1 for a structural zero
 };
 
 namespace heget {

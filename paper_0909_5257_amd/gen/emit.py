@@ -30,6 +30,7 @@ from fractions import Fraction
 
 from .model import Dag, Process
 from .reduce import ColourSpace
+from .tuned import TUNED as _TUNED_TABLE
 
 FLOPS = {   # real floating-point operations per call, counted from the routines
     "vvv": 166, "gggg": 134, "iov": 58,
@@ -54,13 +55,12 @@ FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process a
 MERGE_WAVE_CHUNKS = 8
 MERGE_MAX_PATTERN_CHUNKS = 64
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
-# Per (process, precision) choices that measured faster on MI355X than the defaults above:
-# "externals": "group" rebuilds each external wavefunction inside every group from the LDS
-# momenta (nothing stays live across groups, so a larger budget fits); the default keeps the
-# chunk's external momenta and wavefunctions in registers across its groups.
-TUNED = {
-    ("g g > g g g g", "double"): {"externals": "group", "budget": 256},
-}
+# Per (process, precision) settings that measured faster on MI355X than the defaults above
+# (gen/tuned.py, written by python -m paper_0909_5257_amd.tune): "externals": "group" rebuilds
+# each external wavefunction inside every group from the LDS momenta (nothing stays live across
+# groups, so a larger budget fits); the default keeps the chunk's external momenta and
+# wavefunctions in registers across its groups.  "budget" replaces GROUP_BUDGET.
+TUNED = dict(_TUNED_TABLE)
 
 SIZES = {   # 32-bit registers per value
     "double": {"V": 16, "I": 8, "O": 8, "P": 8, "Q": 0, "inv": 2, "amp": 4, "pl": 8},
@@ -581,7 +581,7 @@ class Emitter:
         """The summed kernel me2_* (every helicity configuration), or with sampled=True the kernel
         me2h_* that evaluates one given helicity configuration per event."""
         sfx = "f64" if prec == "double" else "f32"
-        hel_arg = "const int* __restrict__ hel, " if sampled else ""
+        hel_arg = "const int* __restrict__ hel, const int* __restrict__ perm, " if sampled else ""
         args = (f"const double* __restrict__ mom, {hel_arg}int64_t nev, double* __restrict__ out, "
                 "const double* __restrict__ cmat, double scale")
         nwave = self.nwave[prec]
@@ -595,8 +595,15 @@ class Emitter:
         w(f"__global__ __launch_bounds__({nt}, {min_waves}) void me2{'h' if sampled else ''}_{sfx}({args}) {{")
         w("  const int lane = threadIdx.x & 63;")
         w("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
-        w("  const int64_t ev = (int64_t)blockIdx.x * 64 + lane;")
-        w("  const int64_t evc = ev < nev ? ev : nev - 1;")
+        if sampled:
+            # with perm, slot i of the launch evaluates event perm[i] (events grouped by pattern)
+            w("  const int64_t slot = (int64_t)blockIdx.x * 64 + lane;")
+            w("  const int64_t sc = slot < nev ? slot : nev - 1;")
+            w("  const int64_t evc = perm ? (int64_t)perm[sc] : sc;")
+            w("  const int64_t ev = slot < nev ? evc : nev;      // nev: no output for padding lanes")
+        else:
+            w("  const int64_t ev = (int64_t)blockIdx.x * 64 + lane;")
+            w("  const int64_t evc = ev < nev ? ev : nev - 1;")
         w("  if (wave == 0) {")
         w("    double pm[NEXT][4];")
         w("    load_momenta<NEXT>(mom, evc, pm);")
@@ -703,7 +710,8 @@ class Emitter:
             if prec == "double":
                 args = ("const double* __restrict__ mom, int64_t nev, double* __restrict__ out, "
                         "const double* __restrict__ cmat, double scale")
-                hargs = ("const double* __restrict__ mom, const int* __restrict__ hel, int64_t nev, "
+                hargs = ("const double* __restrict__ mom, const int* __restrict__ hel, const int* __restrict__ perm, "
+                         "int64_t nev, "
                          "double* __restrict__ out, const double* __restrict__ cmat, double scale")
                 w(f"__global__ void me2_f32({args});     // in the mixed translation unit")
                 w(f"__global__ void me2h_f32({hargs});")
@@ -724,8 +732,8 @@ class Emitter:
                  for a in range(self.k) for b in range(self.k)]
         w(f"static const long long k_num_{proc.tag}[] = {{" + ", ".join(str(x[0]) for x in nvals) + "};")
         w(f"static const long long k_den_{proc.tag}[] = {{" + ", ".join(str(x[1]) for x in nvals) + "};")
-        w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, const int* hel, int64_t n, "
-          f"double* out, const double* cmat, double scale, hipStream_t s) {{")
+        w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, const int* hel, const int* perm, "
+          f"int64_t n, double* out, const double* cmat, double scale, hipStream_t s) {{")
         w(f"  const dim3 grid((unsigned)((n + 63) / 64)), "
           f"block(prec == 0 ? {64 * self.nwave['double']} : {64 * self.nwave['float']});")
         w("  if (hel == nullptr) {")
@@ -735,17 +743,22 @@ class Emitter:
         w(f"      hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mom, n, out, cmat, scale);")
         w("  } else {")
         w("    if (prec == 0)")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mom, hel, n, out, cmat, scale);")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
         w("    else")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mom, hel, n, out, cmat, scale);")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
         w("  }")
         w("  return hipGetLastError();")
         w("}")
         nhel = 2 * sum(p.ncfg for p in self.pats)
+        hmap = self.helicity_map()
+        pat_of = [hmap[h if h & 1 else ~h & ((1 << proc.n) - 1)] for h in range(1 << proc.n)]
+        w(f"static const int k_pattern_{proc.tag}[] = {{" + ", ".join(str(c >> 16 if c >= 0 else -1) for c in pat_of)
+          + "};")
         w(f"extern const heget_proc_desc heget_desc_{proc.tag} = {{")
         w(f"  \"{proc.spec}\", {proc.n}, {len(dag.amps)}, {self.k}, {nhel}, {1 << proc.n},")
         w(f"  {len(table)}, k_colour_table_{proc.tag}, k_num_{proc.tag}, k_den_{proc.tag},")
-        w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{proc.tag}}};")
+        w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{proc.tag},")
+        w(f"  {len(self.pats)}, k_pattern_{proc.tag}}};")
         w("#endif")
         out["f64"] = "\n".join(lines) + "\n"
         return out

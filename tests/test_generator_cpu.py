@@ -181,3 +181,32 @@ def test_workgroup_shape_fits_lds_and_meets_occupancy_target(spec):
             half = w // 2
             assert half * (emit.LDS_PER_CU // em.lds_bytes(half)) < emit.TARGET_WAVES_PER_CU[prec]
     assert em.kdim % em.cblock == 0
+
+
+def test_tuner_keeps_only_clear_wins(tmp_path):
+    """apply keeps, per process and precision, the fastest candidate only when it beats the
+    default by more than the margin, and writes a table the planner can read."""
+    import json
+    import runpy
+    from paper_0909_5257_amd import tune
+    timings = {
+        "default": {"g g > g g g|fp64": 10.0, "g g > g g g|mixed": 10.0},
+        "group208": {"g g > g g g|fp64": 9.0, "g g > g g g|mixed": 9.9},
+        "group256": {"g g > g g g|fp64": 9.5, "g g > g g g|mixed": 11.0},
+        "group320": {"g g > g g g|fp64": 12.0, "g g > g g g|mixed": 12.0},
+    }
+    (tmp_path / "timings.json").write_text(json.dumps(timings))
+    table = tmp_path / "tuned.py"
+    chosen = tune.main(["apply", "--out", str(tmp_path), "--table", str(table)])
+    assert set(chosen) == {("g g > g g g", "double")}          # 1 % on mixed is within the margin
+    assert chosen[("g g > g g g", "double")]["budget"] == tune.CANDIDATES["group208"]["double"]["budget"]
+    loaded = runpy.run_path(str(table))["TUNED"]
+    assert loaded[("g g > g g g", "double")]["externals"] == "group"
+
+
+def test_committed_tuned_table_is_valid():
+    from paper_0909_5257_amd.build import PROCESSES
+    from paper_0909_5257_amd.gen.tuned import TUNED
+    for (spec, prec), s in TUNED.items():
+        assert spec in PROCESSES and prec in ("double", "float")
+        assert s.get("externals") in (None, "group") and 64 <= s.get("budget", 176) <= 512

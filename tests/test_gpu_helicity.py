@@ -100,17 +100,42 @@ def test_helicity_mode_sums_to_summed_entry_point(torch_dev, spec):
         assert rel <= (1e-13 if precision == "fp64" else 1e-6)
 
 
-def test_helicity_mode_out_of_range_gives_nan(torch_dev):
+@pytest.mark.parametrize("spec", ["g g > g g g", "u u > u u g"])
+def test_helicity_mode_out_of_range_gives_nan(torch_dev, spec):
+    """Single-pattern processes run in event order; two-quark-line processes sort the events by
+    chirality pattern first (out-of-range patterns sort last): both leave NaN exactly there."""
+    from oracle import oracle_me2
     torch = torch_dev
-    spec = "g g > g g g"
     p, h = _events(spec, 130)
+    n_ext = p.shape[1]
     h = h.copy()
-    h[3], h[77], h[129] = -1, 1 << 5, 1 << 30
+    h[3], h[77], h[129] = -1, 1 << n_ext, 1 << 30
     got = _gpu_hel(torch, spec, "fp64", p, h)
     bad = np.zeros(130, bool)
     bad[[3, 77, 129]] = True
     assert np.all(np.isnan(got[bad]))
     assert np.all(np.isfinite(got[~bad]))
+    full, per_hel = oracle_me2(spec, p, ALPHA_S, return_helicities=True)
+    idx = np.nonzero(~bad)[0]
+    err = np.abs(got[idx] - 0.25 * per_hel[h[idx], idx]) / full[idx]
+    assert err.max() <= TOL["fp64"]
+
+
+def test_helicity_mode_large_batch_two_quark_lines(torch_dev):
+    """A batch of 2^16 events of u u > u u g g with drawn patterns (sorted by chirality pattern
+    inside the library) against the oracle on sampled events."""
+    from oracle import oracle_me2
+    torch = torch_dev
+    spec = "u u > u u g g"
+    n = 1 << 16
+    p, h = _events(spec, n)
+    got = _gpu_hel(torch, spec, "fp64", p, h)
+    idx = np.linspace(0, n - 1, 24).astype(int)
+    full, per_hel = oracle_me2(spec, p[idx], ALPHA_S, return_helicities=True)
+    err = np.abs(got[idx] - 0.25 * per_hel[h[idx], np.arange(len(idx))]) / full
+    _say(f"[helicity] {spec} 2^16 sorted: max err / summed |M|^2 {err.max():.3e}")
+    assert err.max() <= TOL["fp64"]
+    assert np.all(np.isfinite(got))
 
 
 def test_helicity_mode_argument_errors(torch_dev):
