@@ -99,8 +99,12 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
  * sum over all 2^n_ext patterns equals heget_matrix_elements and 2^n_ext * me2
  * is an unbiased estimate of it for uniformly drawn h.  Structural zeros give
  * exactly 0; an h outside [0, 2^n_ext) gives NaN for that event.
+ * For processes with several quark-chirality patterns (two quark lines) and
+ * n_events < 2^31 the events are first sorted by pattern on the device, with
+ * work space of 16 bytes per event plus the sort's own taken from and returned
+ * to the device's stream-ordered pool; results are written in event order.
  * Errors: as heget_matrix_elements, plus HEGET_E_INVALID_ARG for a NULL
- * helicity pointer. */
+ * helicity pointer and HEGET_E_OUT_OF_MEMORY if the sort's work space fails. */
 heget_status heget_matrix_elements_helicity(heget_process_t p, const double* momenta, const int32_t* helicity,
                                             int64_t n_events, double alpha_s, double* me2, void* stream);
 
