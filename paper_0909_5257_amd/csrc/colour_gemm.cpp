@@ -34,7 +34,7 @@ rocblas_handle handle_for(int dev) {
   if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
   g_handles[dev] = h;
   // keep freed work space in the device's stream-ordered pool between calls instead of
-  // returning it to the driver at every synchronisation (re-mapping gigabytes per call)
+  // handing it back to the HIP runtime at every synchronisation (re-mapping gigabytes per call)
   hipMemPool_t pool = nullptr;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
     uint64_t keep = uint64_t(16) << 30;     // up to 16 GiB stays cached
