@@ -353,6 +353,7 @@ class Emitter:
         tuned = {prec: TUNED.get((self.proc.spec, prec), {}) for prec in ("double", "float")}
         self.group_externals = {prec: tuned[prec].get("externals") == "group" for prec in tuned}
         self.budget = {prec: tuned[prec].get("budget", GROUP_BUDGET[prec]) for prec in tuned}
+        self.target_waves = {prec: tuned[prec].get("waves_per_cu", TARGET_WAVES_PER_CU[prec]) for prec in tuned}
         self.nwave = {prec: self.waves_per_workgroup(prec) for prec in ("double", "float")}
         # colour-sum row blocks: the largest block size that still gives every wave two blocks
         most = max(self.nwave.values())
@@ -376,7 +377,7 @@ class Emitter:
             return FORCE_WAVES
         for w in (1, 2, 4, 8):
             per_cu = LDS_PER_CU // self.lds_bytes(w)
-            if per_cu >= 1 and w * per_cu >= TARGET_WAVES_PER_CU[prec]:
+            if per_cu >= 1 and w * per_cu >= self.target_waves[prec]:
                 return w
         return 8
 
@@ -591,7 +592,7 @@ class Emitter:
         # second bound: minimum waves per SIMD, so that the register allocator (kernel and the
         # chunk functions it calls) stays within the occupancy the LDS allows
         lds_waves_per_simd = (LDS_PER_CU // self.lds_bytes(nwave)) * nwave // 4
-        min_waves = max(1, min(TARGET_WAVES_PER_CU[prec] // 4, lds_waves_per_simd))
+        min_waves = max(1, min(self.target_waves[prec] // 4, lds_waves_per_simd))
         w(f"__global__ __launch_bounds__({nt}, {min_waves}) void me2{'h' if sampled else ''}_{sfx}({args}) {{")
         w("  const int lane = threadIdx.x & 63;")
         w("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")

@@ -4,10 +4,12 @@ Timed on one MI355X: 262144 events per launch, seeded RAMBO events with sqrt(s) 
 GeV and the jet cuts; ms = mean of three launches with the setting, default_ms = without it."""
 
 TUNED = {
-    ('g g > g g g g', 'double'): {'externals': 'group', 'budget': 256, 'ms': 26.813, 'default_ms': 31.05},
-    ('g g > g g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 16.399, 'default_ms': 17.466},
-    ('u g > u g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 3.695, 'default_ms': 4.205},
-    ('u u > u u g g', 'float'): {'externals': 'group', 'budget': 208, 'ms': 1.345, 'default_ms': 1.4},
-    ('u u > u u g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 21.542, 'default_ms': 23.936},
-    ('u u~ > g g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 3.675, 'default_ms': 4.284},
+    ('g g > g g g g', 'double'): {'externals': 'group', 'budget': 256, 'ms': 26.813, 'default_ms': 31.104},
+    ('g g > g g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 16.399, 'default_ms': 17.513},
+    ('u g > u g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 3.695, 'default_ms': 4.33},
+    ('u u > u u g g', 'double'): {'externals': 'group', 'budget': 208, 'ms': 1.507, 'default_ms': 1.558},
+    ('u u > u u g g', 'float'): {'externals': 'group', 'budget': 144, 'waves_per_cu': 12, 'ms': 1.32, 'default_ms': 1.431},
+    ('u u > u u g g g', 'double'): {'externals': 'group', 'budget': 176, 'waves_per_cu': 8, 'ms': 36.412, 'default_ms': 37.967},
+    ('u u > u u g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 21.542, 'default_ms': 24.259},
+    ('u u~ > g g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 3.675, 'default_ms': 4.305},
 }

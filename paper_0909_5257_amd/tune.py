@@ -28,6 +28,9 @@ CANDIDATES = {
     "group208": {"double": {"externals": "group", "budget": 208}, "float": {"externals": "group", "budget": 176}},
     "group256": {"double": {"externals": "group", "budget": 256}, "float": {"externals": "group", "budget": 208}},
     "group320": {"double": {"externals": "group", "budget": 320}, "float": {"externals": "group", "budget": 240}},
+    # more resident waves: float64 at two per SIMD, float32 at three
+    "group176w": {"double": {"externals": "group", "budget": 176, "waves_per_cu": 8},
+                  "float": {"externals": "group", "budget": 144, "waves_per_cu": 12}},
 }
 DEFAULT_PROCESSES = ["g g > g g g g", "u u~ > g g g g", "u u~ > g g g g g", "u u > u u g g", "u u > u u g g g",
                      "u g > u g g g"]
@@ -38,9 +41,11 @@ EVENTS = 1 << 18
 def _build(args):
     procs = args.only or DEFAULT_PROCESSES
     os.makedirs(args.out, exist_ok=True)
-    jobs = max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)) // len(CANDIDATES))
+    names = args.candidates or list(CANDIDATES)
+    jobs = max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)) // len(names))
     running = []
-    for name, cand in CANDIDATES.items():       # the candidate builds run side by side
+    for name in names:                          # the candidate builds run side by side
+        cand = CANDIDATES[name]
         env = dict(os.environ)
         env["HEGET_GEN_DIR"] = os.path.join(args.out, f"gen_{name}")
         env["HEGET_BUILD_DIR"] = os.path.join(args.out, f"build_{name}")
@@ -89,8 +94,9 @@ print("RESULT " + json.dumps(out), flush=True)
 
 def _measure(args):
     procs = json.load(open(os.path.join(args.out, "processes.json")))
-    results = {}
-    for name in CANDIDATES:
+    path = os.path.join(args.out, "timings.json")
+    results = json.load(open(path)) if os.path.exists(path) else {}    # earlier candidates are kept
+    for name in args.candidates or list(CANDIDATES):
         lib = os.path.join(args.out, f"lib_{name}.so")
         code = _TIMER.replace("ROOT", repr(ROOT)).replace("SPECS", repr(procs)).replace("EVENTS", str(EVENTS))
         env = dict(os.environ, HEGET_LIB=lib)
@@ -102,7 +108,7 @@ def _measure(args):
             raise SystemExit(f"timing with {name} failed")
         line = [l for l in run.stdout.splitlines() if l.startswith("RESULT ")][-1]
         results[name] = json.loads(line[len("RESULT "):])
-    with open(os.path.join(args.out, "timings.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(results, f, indent=1)
 
 
@@ -116,7 +122,7 @@ def _apply(args):
         base = timings["default"][key]
         best, best_ms = None, base
         for name, t in timings.items():
-            if name != "default" and t[key] < best_ms:
+            if name != "default" and key in t and t[key] < best_ms:
                 best, best_ms = name, t[key]
         print(f"{key:28s} default {base:9.2f} ms  best {best or 'default':9s} {best_ms:9.2f} ms", flush=True)
         if best is not None and best_ms < (1.0 - MARGIN) * base:
@@ -142,6 +148,7 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--only", nargs="*")
     ap.add_argument("--table", default=None, help="output of apply (default: gen/tuned.py)")
+    ap.add_argument("--candidates", nargs="*", help="build / time only these candidates")
     args = ap.parse_args(argv)
     return {"build": _build, "measure": _measure, "apply": _apply}[args.step](args)
 
