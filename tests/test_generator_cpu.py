@@ -176,10 +176,11 @@ def test_workgroup_shape_fits_lds_and_meets_occupancy_target(spec):
         lds = em.lds_bytes(w)
         assert lds <= emit.LDS_PER_CU
         per_cu = emit.LDS_PER_CU // lds
-        assert w * per_cu >= emit.TARGET_WAVES_PER_CU[prec] or w == 8
+        target = em.target_waves[prec]           # the default, or the tuned value for this process
+        assert w * per_cu >= target or w == 8
         if w > 1:       # no smaller shape would have done
             half = w // 2
-            assert half * (emit.LDS_PER_CU // em.lds_bytes(half)) < emit.TARGET_WAVES_PER_CU[prec]
+            assert half * (emit.LDS_PER_CU // em.lds_bytes(half)) < target
     assert em.kdim % em.cblock == 0
 
 
