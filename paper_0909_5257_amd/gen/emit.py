@@ -51,9 +51,9 @@ FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process a
 # traffic), so a wave's consecutive chunks are merged into one called function of up to this many
 # chunks.  Merged functions compile more slowly; patterns with more than MERGE_MAX_PATTERN_CHUNKS
 # chunks (g g > g g g g g) keep one function per chunk so that no translation unit takes much
-# longer than a quarter of an hour.
+# longer than a quarter of an hour (merged, its float64 unit took more than 40 minutes).
 MERGE_WAVE_CHUNKS = 8
-MERGE_MAX_PATTERN_CHUNKS = 64
+MERGE_MAX_PATTERN_CHUNKS = 48
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 # Per (process, precision) settings that measured faster on MI355X than the defaults above
 # (gen/tuned.py, written by python -m paper_0909_5257_amd.tune): "externals": "group" rebuilds
