@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the helicity Monte Carlo, colour GEMM and integration measurements")
+    ap.add_argument("--colour-gemm-only", action="store_true",
+                    help="only the C3 colour GEMM measurement (2^21 rows, K = 120), printed as one JSON line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
     args = ap.parse_args()
@@ -363,6 +365,11 @@ def main():
 
     import torch
     from paper_0909_5257_amd.heget import Process
+
+    if args.colour_gemm_only:
+        print(json.dumps({"colour_gemm_c3": colour_gemm_run(torch, WORKLOAD[1][1], args.steps, args.warmup)}),
+              flush=True)
+        return
 
     # host-side inputs and the oracle baselines first: the all-core baseline forks worker
     # processes, which must happen before this process touches the GPU
