@@ -31,6 +31,9 @@ CANDIDATES = {
     # more resident waves: float64 at two per SIMD, float32 at three
     "group176w": {"double": {"externals": "group", "budget": 176, "waves_per_cu": 8},
                   "float": {"externals": "group", "budget": 144, "waves_per_cu": 12}},
+    # externals kept in registers, other budgets
+    "keep160": {"double": {"budget": 160}, "float": {"budget": 160}},
+    "keep200": {"double": {"budget": 192}, "float": {"budget": 200}},
 }
 DEFAULT_PROCESSES = ["g g > g g g g", "u u~ > g g g g", "u u~ > g g g g g", "u u > u u g g", "u u > u u g g g",
                      "u g > u g g g"]
@@ -107,7 +110,7 @@ def _measure(args):
             sys.stderr.write(run.stderr[-3000:])
             raise SystemExit(f"timing with {name} failed")
         line = [l for l in run.stdout.splitlines() if l.startswith("RESULT ")][-1]
-        results[name] = json.loads(line[len("RESULT "):])
+        results.setdefault(name, {}).update(json.loads(line[len("RESULT "):]))
     with open(path, "w") as f:
         json.dump(results, f, indent=1)
 
