@@ -13,5 +13,6 @@ TUNED = {
     ('u u > u u g g', 'float'): {'externals': 'group', 'budget': 144, 'waves_per_cu': 12, 'ms': 1.32, 'default_ms': 1.431},
     ('u u > u u g g g', 'double'): {'externals': 'group', 'budget': 176, 'waves_per_cu': 8, 'ms': 36.412, 'default_ms': 37.967},
     ('u u > u u g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 21.542, 'default_ms': 24.259},
+    ('u u~ > g g g g g', 'float'): {'budget': 160, 'ms': 99.73, 'default_ms': 106.749},
     ('u u~ > g g g g', 'float'): {'externals': 'group', 'budget': 176, 'ms': 3.675, 'default_ms': 4.305},
 }
