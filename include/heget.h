@@ -153,29 +153,33 @@ heget_status heget_matrix_elements_batch(const heget_batch_item* items, int n_it
 
 /* Precision of the colour contraction in heget_colour_quadratic_form. */
 typedef enum {
-  HEGET_COLOUR_FP64 = 0,    /* float64 GEMM */
-  HEGET_COLOUR_FP32 = 1,    /* float32 GEMM on the matrix cores */
-  HEGET_COLOUR_BF16X3 = 2   /* bf16 hi/lo split, three products, float32 accumulate */
+  HEGET_COLOUR_FP64 = 0,       /* float64 on the matrix cores */
+  HEGET_COLOUR_FP32 = 1,       /* float32 operands on the matrix cores, float32 accumulate */
+  HEGET_COLOUR_BF16X3 = 2,     /* bf16 hi/lo split, three matrix-core products, float32 accumulate */
+  HEGET_COLOUR_FP64_VALU = 3   /* float64 on the vector ALUs (n_colours <= 128) */
 } heget_colour_mode;
 
 /* Colour quadratic form of eq. (color-averaged-amplitude) for many amplitude
  * vectors at once, written as a GEMM: with the real and imaginary parts of J
  * as separate rows X (2R x K), Y = X N and q_r = X_2r.Y_2r + X_2r+1.Y_2r+1.
- * This is the colour step of the paper in its own basis, offered for precision
- * and speed studies of the contraction (the process kernels do the same sum in
- * an exactly reduced colour space).
- *   n_colours     K > 0.
+ * This is the colour step of the paper in its own basis (section 3.3: eq.
+ * color-matrix, Table 3), offered for precision and speed studies of the
+ * contraction (the process kernels do the same sum in an exactly reduced
+ * colour space).
+ *   n_colours     K > 0 (K > 128 only for the three matrix-core modes).
  *   colour_matrix DEVICE float64 K x K, symmetric (e.g. heget_color_matrix values).
  *   jamp          DEVICE float64 [rows][2][K]: Re J then Im J of each row.
- *   rows          number of amplitude vectors R, 0 <= R <= 2^30.
- *   mode          HEGET_COLOUR_FP64 / _FP32 / _BF16X3.
+ *   rows          number of amplitude vectors R, 0 <= R < 2^30.
+ *   mode          HEGET_COLOUR_FP64 / _FP32 / _BF16X3 / _FP64_VALU.
  *   q             DEVICE float64 [rows], written.
  *   stream        hipStream_t (NULL: default stream).
- * Work space (at most 1.25 times the bytes of jamp) is taken from and
- * returned to the device's default stream-ordered memory pool; the first call
- * on a device sets that pool to keep up to 16 GiB of freed memory cached for
- * later calls.  The row-wise dot is always accumulated in float64 against the
- * float64 J.  Errors: HEGET_E_INVALID_ARG, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
+ * For K <= 128 hand-written kernels read J once and need no work space.  For
+ * K > 128 the product is a library GEMM whose work space (at most 1.25 times
+ * the bytes of jamp) is taken from and returned to the device's default
+ * stream-ordered memory pool (the first such call on a device sets that pool
+ * to keep up to 16 GiB of freed memory cached).  The row-wise dot is always
+ * accumulated in float64 against the float64 J.
+ * Errors: HEGET_E_INVALID_ARG, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
 heget_status heget_colour_quadratic_form(int n_colours, const double* colour_matrix, const double* jamp,
                                          int64_t rows, heget_colour_mode mode, double* q, void* stream);
 
@@ -241,8 +245,59 @@ heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const dou
                                   const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
                                   double* me2, double* weight, double* sums, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Test hooks (not on the hot path).  They let a test compare the amplitudes
+ * themselves, not only |M|^2, with an independent implementation.
+ * ------------------------------------------------------------------------- */
+
+/* The reduced colour space the kernels accumulate in.  The kernels never form
+ * the K colour-basis amplitudes J of eq. (color-amplitude) explicitly: they add
+ * every diagram into y = M J, a vector of K' <= K components (M exact,
+ * rational), and evaluate the colour sum of eq. (color-averaged-amplitude) as
+ * y^H W y, which equals J^H N J exactly.  The kernels evaluate n_slots helicity
+ * configurations per event (leg 0 at helicity +1, structural zeros of massless
+ * quark chirality skipped; the all-flipped configurations give the same colour
+ * sum and are accounted for by a factor 2).
+ *   k_reduced, n_slots  receive K' and the number of evaluated configurations
+ *                       (required).
+ *   m_num, m_den        HOST int64 [K' * K] or NULL: M = m_num / m_den, row-major.
+ *   w_num, w_den        HOST int64 [K' * K'] or NULL: W = w_num / w_den, row-major.
+ *   slot_helicity       HOST int32 [n_slots] or NULL: the helicity bit pattern of
+ *                       each configuration (bit i set: leg i at +1), in the
+ *                       order of the jamp output of heget_matrix_elements_hook.
+ * Errors: HEGET_E_INVALID_ARG for a NULL handle, k_reduced or n_slots. */
+heget_status heget_colour_reduction(heget_process_t p, int* k_reduced, int* n_slots, int64_t* m_num,
+                                    int64_t* m_den, int64_t* w_num, int64_t* w_den, int32_t* slot_helicity);
+
+/* heget_matrix_elements through the test-hook kernels, which are generated
+ * from the same diagram graph, routines and colour reduction as the hot-path
+ * kernels, for processes with at most six legs, in the handle's precision.
+ *   gauge_leg  -1, or the index of a gluon leg whose polarisation vector is
+ *              replaced by its momentum divided by its energy (eps -> k/E).
+ *              Current conservation (section 4: the three- and four-gluon
+ *              vertices of eqs. vvv-amplitude and gggg-amplitude and the qqg
+ *              vertex of eq. qqg-amplitude, with the colour factors of
+ *              section 2.1) makes every helicity amplitude, and so me2, vanish
+ *              up to rounding; a wrong relative sign or colour factor between
+ *              diagram types does not.
+ *   me2        DEVICE float64 [n_events], written (as heget_matrix_elements).
+ *   jamp       DEVICE float64 [n_events][n_slots][K'][2] or NULL: the reduced
+ *              colour vector y (real, imaginary part) of every evaluated
+ *              configuration, with couplings set to 1: the amplitudes carry
+ *              g_s^(n-2) less than eq. (color-amplitude) and phase conventions
+ *              of the external states of their own, so y equals
+ *              c * M J for one complex c of modulus g_s^-(n-2) per event and
+ *              configuration.
+ * Other arguments as heget_matrix_elements.
+ * Errors: HEGET_E_UNSUPPORTED_PROCESS (no test-hook kernels for this process),
+ * HEGET_E_INVALID_ARG (gauge_leg not -1 and not a gluon leg, or as
+ * heget_matrix_elements), HEGET_E_DEVICE. */
+heget_status heget_matrix_elements_hook(heget_process_t p, const double* momenta, int64_t n_events, double alpha_s,
+                                        int gauge_leg, double* me2, double* jamp, void* stream);
+
 /* Release a handle and its device state.  NULL is ignored.  The caller must
- * make sure no queued work still uses the handle. */
+ * make sure no queued work still uses the handle.  Cached batch graphs that
+ * launch the handle's kernels are destroyed with it. */
 void heget_destroy_process(heget_process_t p);
 
 /* Static description of a status code. */

@@ -37,6 +37,10 @@ PROCESSES = [
     "u u~ > u u~",
 ]
 
+# processes with at most this many legs also get the test-hook kernels (gauge substitution and
+# colour-vector export, include/heget.h heget_matrix_elements_hook)
+HOOK_MAX_LEGS = 6
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -83,14 +87,18 @@ def generate(specs, verbose=True):
         t0 = time.time()
         dag = Dag(parse(spec))
         nmat = dag.colour_matrix()
-        srcs = Emitter(dag, nmat).emit()
+        hook = dag.proc.n <= HOOK_MAX_LEGS
+        srcs = Emitter(dag, nmat).emit(with_hook=hook)
+        if hook:
+            srcs["hook"] = Emitter(dag, nmat, hook=True).emit_hook()
         for part, src in srcs.items():
             path = os.path.join(GEN_DIR, f"proc_{dag.proc.tag}_{part}.hip")
             _write_if_changed(path, src)
             files.append(path)
         tags.append(dag.proc.tag)
         if verbose:
-            print(f"[gen] {spec:22s} -> proc_{dag.proc.tag}_{{f64,f32}}.hip ({time.time() - t0:.1f}s)", flush=True)
+            print(f"[gen] {spec:22s} -> proc_{dag.proc.tag}_{{{','.join(srcs)}}}.hip ({time.time() - t0:.1f}s)",
+                  flush=True)
     # drop generated sources of processes (or layouts) this build does not contain
     for name in os.listdir(GEN_DIR):
         path = os.path.join(GEN_DIR, name)
@@ -114,10 +122,30 @@ def _write_if_changed(path, text):
         f.write(text)
 
 
+def _local_includes(path, seen):
+    """path and every file it includes with #include "..." from csrc/ or include/, recursively."""
+    if path in seen:
+        return
+    seen.append(path)
+    for line in open(path, errors="replace"):
+        line = line.strip()
+        if line.startswith("#include \""):
+            name = line.split('"')[1]
+            for d in (CSRC, os.path.join(ROOT, "include")):
+                cand = os.path.join(d, name)
+                if os.path.exists(cand):
+                    _local_includes(cand, seen)
+                    break
+
+
 def _digest(src, cmd):
+    """Digest of the command, the source and the local headers it includes (so that editing the
+    public header does not recompile the generated process units, which never include it)."""
     h = hashlib.sha256(" ".join(cmd).encode())
-    for path in [src] + [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hpp")] + \
-            [os.path.join(ROOT, "include", "heget.h")]:
+    files = []
+    _local_includes(src, files)
+    for path in files:
+        h.update(path.encode())
         h.update(open(path, "rb").read())
     return h.hexdigest()
 

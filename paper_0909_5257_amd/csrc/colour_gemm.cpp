@@ -1,23 +1,32 @@
-// Colour quadratic form as a GEMM: q_r = sum_{a,b} J_ra N_ab J_rb^* for many rows.
+// Colour quadratic form of the paper's eq. (color-averaged-amplitude) for many amplitude
+// vectors: q_r = sum_{a,b} J_ra N_ab J_rb^* with N real symmetric.  With the real and
+// imaginary parts of J as separate real rows x (2R rows of K), q_r is the sum of x^T N x over
+// the two rows of r, i.e. the GEMM Y = X N followed by a row-wise dot (section 3.3 blames this
+// step for much of the GPU time).
 //
-// The paper's eq. (color-averaged-amplitude) contracts every colour-basis
-// amplitude vector with the real symmetric colour matrix.  Written with the
-// real and imaginary parts of J as separate rows X (2R x K), it is
-// Y = X N followed by a row-wise dot q_r = X_2r . Y_2r + X_2r+1 . Y_2r+1.
-// Three precisions of the contraction are offered for study:
-//   HEGET_COLOUR_FP64    float64 GEMM,
-//   HEGET_COLOUR_FP32    float32 GEMM on the matrix cores,
-//   HEGET_COLOUR_BF16X3  bf16 split X = Xh + Xl, N = Nh + Nl, with
-//                        Y ~ Xh Nh + Xh Nl + Xl Nh in one bf16 GEMM over the
-//                        concatenated inner dimension 3K, float32 accumulate.
-// The GEMMs are plain library GEMMs (rocBLAS); the split and the dot are
-// kernels here.  The dot always accumulates in float64 against the float64 X.
+// For K <= 128 the contraction runs in hand-written gfx950 kernels that read J from HBM once,
+// convert it in registers and keep N in LDS (no work space, nothing staged in HBM):
+//   HEGET_COLOUR_FP64       v_mfma_f64_16x16x4_f64,
+//   HEGET_COLOUR_FP32       v_mfma_f32_16x16x4_f32 (float32 operands, float32 accumulate),
+//   HEGET_COLOUR_BF16X3     v_mfma_f32_16x16x32_bf16 three times per product: x and N split
+//                           into bf16 high and low parts, x N ~ xh Nh + xh Nl + xl Nh,
+//                           float32 accumulate,
+//   HEGET_COLOUR_FP64_VALU  float64 vector FMAs (the same sum without the matrix cores).
+// Symmetry halves the matrix work: with 16-colour blocks, q = sum_{A<=B} x_A^T W_AB x_B where
+// W_AB = 2 N_AB above the diagonal and N_AA on it.  Each MFMA tile computes
+// Y^T[m][t] = sum_a W[a][m] x_t[a] for 16 output colours m and 16 rows t; the inner colours of
+// one instruction are ordered so that each lane already holds, as its MFMA operand, exactly the
+// four x values its four output elements must be dotted with, so the row dot needs no data
+// movement.  The dot is accumulated in float64 against the float64 x in every mode.
+// Larger K falls back to a plain library GEMM (rocBLAS) plus a row-dot kernel.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "heget.h"
@@ -92,16 +101,264 @@ __global__ __launch_bounds__(256) void row_dot(const double* __restrict__ x, con
 
 inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// ---------------------------------------------------------------- hand-written kernels (K <= 128)
+
+constexpr int kMaxK = 128;          // colours: at most 8 blocks of 16
+constexpr int kNB = kMaxK / 16;
+constexpr int kWaves = 4;           // waves per workgroup
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// Symmetrised block weight: W_ab = 2 N_ab if block(a) < block(b), N_ab if the blocks are equal,
+// 0 below the block diagonal or outside the K x K matrix.
+__device__ __forceinline__ double wsym(const double* __restrict__ n, int k, int a, int b) {
+  if (a >= k || b >= k) return 0.0;
+  const int ba = a >> 4, bb = b >> 4;
+  if (ba > bb) return 0.0;
+  const double v = n[(int64_t)a * k + b];
+  return ba < bb ? 2.0 * v : v;
+}
+
+// Wave tile: 16 real rows.  Lane l works on row t = l % 16 and lane group g = l / 16.
+// x[A][s] = x_t[16 A + 4 g + s]: the MFMA B operand of inner step s of block A (inner index g of
+// the instruction is colour 16 A + 4 g + s) and, for output block B = A, the four values that
+// the lane's output elements D[i] = Y^T[16 B + 4 g + i][t] are dotted with.
+__device__ __forceinline__ void load_tile(const double* __restrict__ x, int k, int64_t nreal, int64_t r0, int lane,
+                                          double (&xv)[kNB][4]) {
+  const int64_t row = r0 + (lane & 15);
+  const int g = lane >> 4;
+  const bool ok = row < nreal;
+  const double* src = x + row * k;
+#pragma unroll
+  for (int a = 0; a < kNB; ++a)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int c = 16 * a + 4 * g + s;
+      xv[a][s] = (ok && c < k) ? src[c] : 0.0;
+    }
+}
+
+// Sum the row partials of the four lane groups, add the two real rows of each amplitude row and
+// write q for the tile's 8 amplitude rows.
+__device__ __forceinline__ void finish_tile(double dot, int lane, int64_t r0, int64_t nreal, double* __restrict__ q) {
+  dot += __shfl_xor(dot, 16, 64);
+  dot += __shfl_xor(dot, 32, 64);
+  dot += __shfl_xor(dot, 1, 64);
+  const int64_t row = r0 + lane;
+  if (lane < 16 && !(lane & 1) && row < nreal) q[row >> 1] = dot;
+}
+
+// float64 / float32 operands, 16x16x4 instructions.
+template <class T>
+__global__ __launch_bounds__(64 * kWaves) void qf_mfma4(int k, const double* __restrict__ nmat,
+                                                          const double* __restrict__ x, int64_t nreal,
+                                                          double* __restrict__ q) {
+  // W in A-operand order: per block pair (A <= B) and inner step s, the 64 lane values
+  __shared__ T ws[kNB * (kNB + 1) / 2 * 4 * 64];
+  const int nb = (k + 15) >> 4;
+  const int npair = nb * (nb + 1) / 2;
+  for (int e = threadIdx.x; e < npair * 256; e += 64 * kWaves) {
+    const int p = e >> 8, s = (e >> 6) & 3, l = e & 63;
+    int bb = 0;
+    while ((bb + 1) * (bb + 2) / 2 <= p) ++bb;
+    const int ba = p - bb * (bb + 1) / 2;
+    ws[e] = (T)wsym(nmat, k, 16 * ba + 4 * (l >> 4) + s, 16 * bb + (l & 15));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (nreal + 15) >> 4;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t r0 = tile * 16;
+    double xv[kNB][4];
+    load_tile(x, k, nreal, r0, lane, xv);
+    double dot = 0.0;
+#pragma unroll
+    for (int b = 0; b < kNB; ++b) {
+      if (b < nb) {
+        using V = typename std::conditional<sizeof(T) == 8, d4_t, f4_t>::type;
+        V acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int a = 0; a <= b; ++a)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const T w = ws[((b * (b + 1) / 2 + a) * 4 + s) * 64 + lane];
+            if constexpr (sizeof(T) == 8)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w, xv[a][s], acc, 0, 0, 0);
+            else
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w, (float)xv[a][s], acc, 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dot += (double)acc[i] * xv[b][i];
+      }
+    }
+    finish_tile(dot, lane, r0, nreal, q);
+  }
+}
+
+__device__ __forceinline__ void split_bf16(double v, __bf16& hi, __bf16& lo) {
+  const float f = (float)v;
+  hi = (__bf16)f;
+  lo = (__bf16)(f - (float)hi);
+}
+
+// bf16 hi/lo split, three 16x16x32 instructions per product.  Inner index 8 g + j of an
+// instruction over 32-colour block A2 is colour 16 (2 A2) + 4 g + j for j < 4 and
+// 16 (2 A2 + 1) + 4 g + (j - 4) otherwise, so the B operand is (x[2 A2][0..3], x[2 A2 + 1][0..3]).
+__global__ __launch_bounds__(64 * kWaves) void qf_mfma_bf16x3(int k, const double* __restrict__ nmat,
+                                                              const double* __restrict__ x, int64_t nreal,
+                                                              double* __restrict__ q) {
+  // per (output block B, inner 32-block A2 <= B / 2): [hi | lo][lane] of 8 bf16
+  constexpr int kPairs = (kNB / 2) * (kNB / 2 + 1);      // sum over B of (B / 2 + 1) = 20 for 8 blocks
+  __shared__ bf8_t ws[kPairs * 2 * 64];
+  const int nb = (k + 15) >> 4;
+  for (int e = threadIdx.x; e < kPairs * 64; e += 64 * kWaves) {
+    const int p = e >> 6, l = e & 63;
+    // pair p -> (B, A2) in the order B = 0.., A2 = 0..B/2
+    int bb = 0, base = 0;
+    while (base + bb / 2 + 1 <= p) {
+      base += bb / 2 + 1;
+      ++bb;
+    }
+    const int a2 = p - base;
+    bf8_t hi, lo;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int a = 16 * (2 * a2 + (j >> 2)) + 4 * (l >> 4) + (j & 3);
+      const double w = bb < nb ? wsym(nmat, k, a, 16 * bb + (l & 15)) : 0.0;
+      __bf16 h, o;
+      split_bf16(w, h, o);
+      hi[j] = h;
+      lo[j] = o;
+    }
+    ws[(p * 2) * 64 + l] = hi;
+    ws[(p * 2 + 1) * 64 + l] = lo;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (nreal + 15) >> 4;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t r0 = tile * 16;
+    double xv[kNB][4];
+    load_tile(x, k, nreal, r0, lane, xv);
+    bf8_t xh[kNB / 2], xl[kNB / 2];
+#pragma unroll
+    for (int a2 = 0; a2 < kNB / 2; ++a2)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        __bf16 h, o;
+        split_bf16(xv[2 * a2 + (j >> 2)][j & 3], h, o);
+        xh[a2][j] = h;
+        xl[a2][j] = o;
+      }
+    double dot = 0.0;
+#pragma unroll
+    for (int b = 0; b < kNB; ++b) {
+      if (b < nb) {
+        f4_t acc = {0, 0, 0, 0};
+        const int base = (b / 2) * (b / 2 + 1) + (b & 1) * (b / 2 + 1);   // pairs before output block b
+#pragma unroll
+        for (int a2 = 0; a2 <= b / 2; ++a2) {
+          const bf8_t wh = ws[((base + a2) * 2) * 64 + lane];
+          const bf8_t wl = ws[((base + a2) * 2 + 1) * 64 + lane];
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh[a2], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl[a2], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh[a2], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dot += (double)acc[i] * xv[b][i];
+      }
+    }
+    finish_tile(dot, lane, r0, nreal, q);
+  }
+}
+
+// float64 on the vector ALUs: a workgroup stages 64 real rows transposed in LDS (one per lane);
+// wave w takes the 8-colour row blocks w, w + 4, ... of the symmetric form
+// q_t = sum_a x_ta (N_aa x_ta + 2 sum_{b > a} N_ab x_tb), N read with wave-uniform scalar loads.
+__global__ __launch_bounds__(64 * kWaves) void qf_valu_f64(int k, const double* __restrict__ nmat,
+                                                           const double* __restrict__ x, int64_t nreal,
+                                                           double* __restrict__ q) {
+  __shared__ double xs[kMaxK][64];
+  __shared__ double part[kWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kp = (k + 7) & ~7;
+  const int64_t ntiles = (nreal + 63) >> 6;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * 64;
+    const int64_t nrow = nreal - r0 < 64 ? nreal - r0 : 64;
+    const double* src = x + r0 * k;
+    for (int e = threadIdx.x; e < 64 * kp; e += 64 * kWaves) {
+      const int t = e / kp, c = e - t * kp;
+      xs[c][t] = (t < nrow && c < k) ? src[(int64_t)t * k + c] : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int a0 = 8 * wave; a0 < k; a0 += 8 * kWaves) {
+      double tr[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tr[i] = 0.0;
+      for (int b = a0; b < k; ++b) {
+        const double xb = xs[b][lane];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int a = a0 + i;
+          const double w = (a < k && b >= a) ? (b == a ? 1.0 : 2.0) * nmat[(int64_t)a * k + b] : 0.0;
+          tr[i] += w * xb;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += xs[a0 + i][lane] * tr[i];
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += part[w][lane];
+      t += __shfl_xor(t, 1, 64);
+      if (!(lane & 1) && lane < nrow) q[(r0 + lane) >> 1] = t;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_hand_written(int k, const double* nmat, const double* jamp, int64_t rows, heget_colour_mode mode,
+                               double* q, hipStream_t s) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t nreal = 2 * rows;
+  if (mode == HEGET_COLOUR_FP64_VALU) {
+    const int64_t tiles = (nreal + 63) / 64;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, (int64_t)cus * 2);
+    hipLaunchKernelGGL(qf_valu_f64, dim3(grid), dim3(64 * kWaves), 0, s, k, nmat, jamp, nreal, q);
+    return hipGetLastError();
+  }
+  const int64_t tiles = (nreal + 15) / 16;
+  const unsigned grid = (unsigned)std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)cus * 8);
+  if (mode == HEGET_COLOUR_FP64)
+    hipLaunchKernelGGL(qf_mfma4<double>, dim3(grid), dim3(64 * kWaves), 0, s, k, nmat, jamp, nreal, q);
+  else if (mode == HEGET_COLOUR_FP32)
+    hipLaunchKernelGGL(qf_mfma4<float>, dim3(grid), dim3(64 * kWaves), 0, s, k, nmat, jamp, nreal, q);
+  else
+    hipLaunchKernelGGL(qf_mfma_bf16x3, dim3(grid), dim3(64 * kWaves), 0, s, k, nmat, jamp, nreal, q);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" heget_status heget_colour_quadratic_form(int k, const double* nmat, const double* jamp, int64_t rows,
                                                     heget_colour_mode mode, double* q, void* stream) {
-  if (k <= 0 || rows < 0 || rows > (int64_t(1) << 31) / 2) return HEGET_E_INVALID_ARG;
-  if (mode != HEGET_COLOUR_FP64 && mode != HEGET_COLOUR_FP32 && mode != HEGET_COLOUR_BF16X3)
+  if (k <= 0 || rows < 0 || rows >= (int64_t(1) << 30)) return HEGET_E_INVALID_ARG;
+  if (mode != HEGET_COLOUR_FP64 && mode != HEGET_COLOUR_FP32 && mode != HEGET_COLOUR_BF16X3 &&
+      mode != HEGET_COLOUR_FP64_VALU)
     return HEGET_E_INVALID_ARG;
+  if (mode == HEGET_COLOUR_FP64_VALU && k > kMaxK) return HEGET_E_INVALID_ARG;
   if (rows == 0) return HEGET_OK;
   if (!nmat || !jamp || !q) return HEGET_E_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (k <= kMaxK) return launch_hand_written(k, nmat, jamp, rows, mode, q, s) == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+  // larger colour spaces: library GEMM (rocBLAS) into a stream-ordered work space, then the row dot
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return HEGET_E_DEVICE;
   std::lock_guard<std::mutex> lock(g_mutex);

@@ -6,6 +6,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -27,9 +28,13 @@ struct heget_process {
   int device;
   double* colour_table_dev;
   int* pattern_dev;      // helicity bit pattern -> chirality pattern (processes with several)
+  uint64_t serial;       // unique per handle ever created (cached graphs are keyed by it)
 };
 
 namespace {
+
+std::atomic<uint64_t> g_next_serial{1};
+void forget_graphs_of(uint64_t serial);
 
 std::string normalise(const char* spec) {
   std::istringstream in(spec);
@@ -70,7 +75,7 @@ heget_status heget_create_process(const char* spec, heget_precision precision, h
   if (precision != HEGET_FP64 && precision != HEGET_MIXED) return HEGET_E_INVALID_ARG;
   const heget_proc_desc* d = find(normalise(spec));
   if (!d) return HEGET_E_UNSUPPORTED_PROCESS;
-  heget_process* p = new (std::nothrow) heget_process{d, (int)precision, 0, nullptr, nullptr};
+  heget_process* p = new (std::nothrow) heget_process{d, (int)precision, 0, nullptr, nullptr, g_next_serial++};
   if (!p) return HEGET_E_OUT_OF_MEMORY;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -147,7 +152,7 @@ heget_status heget_matrix_elements_helicity(heget_process_t p, const double* mom
   // one term of the helicity sum: 1/4 initial spin average and the couplings, no flip factor
   const double scale = 0.25 * std::pow(g2, p->desc->n_ext - 2);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (p->pattern_dev == nullptr || n_events >= (int64_t(1) << 31)) {
+  if (p->pattern_dev == nullptr || n_events >= (int64_t(1) << 31) || n_events > p->desc->max_launch_events) {
     hipError_t e = p->desc->launch(p->precision, momenta, helicity, nullptr, n_events, me2, p->colour_table_dev,
                                    scale, s);
     return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
@@ -183,6 +188,57 @@ heget_status heget_matrix_elements_helicity(heget_process_t p, const double* mom
   return st;
 }
 
+heget_status heget_matrix_elements_hook(heget_process_t p, const double* momenta, int64_t n_events, double alpha_s,
+                                        int gauge_leg, double* me2, double* jamp, void* stream) {
+  if (!p) return HEGET_E_INVALID_ARG;
+  if (!p->desc->launch_hook) return HEGET_E_UNSUPPORTED_PROCESS;
+  if (n_events < 0 || n_events > (int64_t(1) << 36)) return HEGET_E_INVALID_ARG;
+  if (!(alpha_s > 0.0) || !std::isfinite(alpha_s)) return HEGET_E_INVALID_ARG;
+  if (gauge_leg < -1 || gauge_leg >= p->desc->n_ext) return HEGET_E_INVALID_ARG;
+  if (gauge_leg >= 0) {
+    // only gluon legs carry a polarisation vector
+    std::istringstream in(p->desc->spec);
+    std::string tok;
+    int leg = 0;
+    bool gluon = false;
+    while (in >> tok) {
+      if (tok == ">") continue;
+      if (leg++ == gauge_leg) gluon = tok == "g";
+    }
+    if (!gluon) return HEGET_E_INVALID_ARG;
+  }
+  if (n_events == 0) return HEGET_OK;
+  if (!momenta || !me2) return HEGET_E_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(momenta) & 15u) != 0) return HEGET_E_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HEGET_E_DEVICE;
+  if (dev != p->device) return HEGET_E_INVALID_ARG;
+  const double scale = 2.0 * 0.25 * std::pow(4.0 * M_PI * alpha_s, p->desc->n_ext - 2);
+  hipError_t e = p->desc->launch_hook(p->precision, momenta, n_events, me2, p->colour_table_dev, scale, gauge_leg,
+                                      jamp, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+}
+
+heget_status heget_colour_reduction(heget_process_t p, int* k_reduced, int* n_slots, int64_t* m_num, int64_t* m_den,
+                                    int64_t* w_num, int64_t* w_den, int32_t* slot_helicity) {
+  if (!p || !k_reduced || !n_slots) return HEGET_E_INVALID_ARG;
+  const heget_proc_desc* d = p->desc;
+  *k_reduced = d->k_reduced;
+  *n_slots = d->n_slots;
+  const int64_t nm = (int64_t)d->k_reduced * d->n_colours, nw = (int64_t)d->k_reduced * d->k_reduced;
+  for (int64_t i = 0; i < nm; ++i) {
+    if (m_num) m_num[i] = d->red_num[i];
+    if (m_den) m_den[i] = d->red_den[i];
+  }
+  for (int64_t i = 0; i < nw; ++i) {
+    if (w_num) w_num[i] = d->w_num[i];
+    if (w_den) w_den[i] = d->w_den[i];
+  }
+  if (slot_helicity)
+    for (int i = 0; i < d->n_slots; ++i) slot_helicity[i] = d->slot_helicity[i];
+  return HEGET_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -201,6 +257,7 @@ struct DevicePool {
 struct GraphEntry {
   hipGraphExec_t exec;
   uint64_t last_use;
+  std::vector<uint64_t> serials;   // handles the captured launches use
 };
 
 std::mutex g_batch_mutex;
@@ -269,11 +326,33 @@ hipError_t enqueue_batch(DevicePool* pool, const heget_batch_item* items, int n,
   return hipSuccess;
 }
 
+// Key of a captured batch: device, alpha_s and per item the handle's serial (never reused, unlike
+// the handle's address), the buffers and the size.
 std::string batch_key(const heget_batch_item* items, int n, double alpha_s, int dev) {
   std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
   key.append(reinterpret_cast<const char*>(&alpha_s), sizeof(alpha_s));
-  key.append(reinterpret_cast<const char*>(items), sizeof(heget_batch_item) * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const uint64_t serial = items[i].process->serial;
+    key.append(reinterpret_cast<const char*>(&serial), sizeof(serial));
+    key.append(reinterpret_cast<const char*>(&items[i].momenta), sizeof(items[i].momenta));
+    key.append(reinterpret_cast<const char*>(&items[i].n_events), sizeof(items[i].n_events));
+    key.append(reinterpret_cast<const char*>(&items[i].me2), sizeof(items[i].me2));
+  }
   return key;
+}
+
+// Drop every cached graph that launches a kernel of the handle with this serial.
+void forget_graphs_of(uint64_t serial) {
+  std::lock_guard<std::mutex> lock(g_batch_mutex);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    const auto& ser = it->second.serials;
+    if (std::find(ser.begin(), ser.end(), serial) != ser.end()) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 }  // namespace
@@ -323,7 +402,9 @@ heget_status heget_matrix_elements_batch(const heget_batch_item* items, int n_it
       (void)hipGraphExecDestroy(victim->second.exec);
       g_graphs.erase(victim);
     }
-    it = g_graphs.emplace(key, GraphEntry{exec, 0}).first;
+    std::vector<uint64_t> serials;
+    for (int i = 0; i < n_items; ++i) serials.push_back(items[i].process->serial);
+    it = g_graphs.emplace(key, GraphEntry{exec, 0, std::move(serials)}).first;
   }
   it->second.last_use = ++g_graph_clock;
   // order the replay after and before the caller's stream
@@ -355,6 +436,7 @@ heget_status heget_process_flops(heget_process_t p, int64_t* flops_per_event) {
 
 void heget_destroy_process(heget_process_t p) {
   if (!p) return;
+  forget_graphs_of(p->serial);
   if (p->colour_table_dev) (void)hipFree(p->colour_table_dev);
   if (p->pattern_dev) (void)hipFree(p->pattern_dev);
   delete p;

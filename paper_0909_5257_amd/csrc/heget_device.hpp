@@ -96,6 +96,22 @@ template <class R> HD vec4<R> vxxxx0(const mom4<double>& p, int lam, bool outgoi
   return e;
 }
 
+// Test-hook form of vxxxx0: with gauge set the polarisation is replaced by the gluon's momentum
+// over its energy, the substitution under which every amplitude must vanish (current
+// conservation, section 4: eq. vvv-amplitude and the qqg vertex); otherwise vxxxx0.
+template <class R> HD vec4<R> vxxxx0g(const mom4<double>& p, int lam, bool outgoing, bool gauge) {
+  if (gauge) {
+    const double ie = 1.0 / p.e;
+    vec4<R> k;
+    k.c0 = {R(1), R(0)};
+    k.c1 = {R(p.x * ie), R(0)};
+    k.c2 = {R(p.y * ie), R(0)};
+    k.c3 = {R(p.z * ie), R(0)};
+    return k;
+  }
+  return vxxxx0<R>(p, lam, outgoing);
+}
+
 // sqrt(2E) xi_h(p) for a massless momentum
 template <class R, int H> HD wsp<R> weyl_xi(const mom4<double>& p) {
   double rho = p.e + p.z;

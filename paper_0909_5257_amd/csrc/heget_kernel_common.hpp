@@ -26,6 +26,18 @@ struct heget_proc_desc {
                        double* out, const double* colour_table_dev, double scale, hipStream_t stream);
   int n_patterns;                // quark-chirality patterns of the sampled-helicity kernels
   const int* helicity_pattern;   // per bit pattern h: its chirality pattern, -1 for a structural zero
+  int k_reduced;                 // dimension K' of the reduced colour vector y the kernels accumulate
+  int n_slots;                   // evaluated helicity configurations (leg 0 at +1, no structural zeros)
+  const int* slot_helicity;      // helicity bit pattern of each evaluated configuration, loop order
+  const long long* red_num;      // y = M J, M = red_num / red_den (K' x K, row-major)
+  const long long* red_den;
+  const long long* w_num;        // Q = y^H W y, W = w_num / w_den (K' x K', row-major)
+  const long long* w_den;
+  // test-hook kernels (nullptr if not generated): gauge leg substitution eps -> k/E (-1: none) and,
+  // with jamp != nullptr, y of every evaluated configuration as float64 [n][n_slots][K'][2]
+  hipError_t (*launch_hook)(int precision, const double* mom, int64_t n, double* out, const double* colour_table_dev,
+                            double scale, int gauge, double* jamp, hipStream_t stream);
+  long long max_launch_events;   // events one kernel launch covers (larger batches run in slices)
 };
 
 namespace heget {

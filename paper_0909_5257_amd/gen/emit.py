@@ -270,7 +270,7 @@ class _Group:
                     lam = str(self.pat.fixed[leg.index])
                 else:
                     lam = f"((cfg >> {self.pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
-                expr = f"vxxxx0<R>({pl}, {lam}, {'false' if leg.incoming else 'true'})"
+                expr = em.gluon_ext(pl, lam, leg)
             elif leg.kind == "I":
                 typ = "wsp<R>"
                 expr = f"ixxxx0<R, {h[leg.index]}>({pl})"
@@ -341,10 +341,16 @@ class _Group:
 
 
 class Emitter:
-    def __init__(self, dag: Dag, nmat):
+    """Sources of one process.  With hook=True the emitter writes the test-hook kernels instead
+    (me2x_*: every gluon external can be replaced by its momentum, and the reduced colour vector
+    of every evaluated configuration can be written out); the hot-path kernels never carry
+    that switch, so the compiler keeps folding the vanishing polarisation components."""
+
+    def __init__(self, dag: Dag, nmat, hook: bool = False):
         self.dag = dag
         self.proc = dag.proc
         self.nmat = nmat
+        self.hook = hook
         self.k = len(dag.basis)
         self.cs = ColourSpace(dag, nmat)
         self.kdim = self.cs.dim
@@ -362,6 +368,54 @@ class Emitter:
         self.flops = {"double": 0, "float": 0}
         self.algo_flops = 0
         self.stats = {}
+
+    def gluon_ext(self, pl: str, lam: str, leg) -> str:
+        """Expression of one external gluon polarisation (physical momentum pl, helicity lam)."""
+        out = "false" if leg.incoming else "true"
+        if self.hook:
+            return f"vxxxx0g<R>({pl}, {lam}, {out}, gauge == {leg.index})"
+        return f"vxxxx0<R>({pl}, {lam}, {out})"
+
+    @property
+    def chunk_params(self) -> str:
+        return "int cfg, int lane, int gauge" if self.hook else "int cfg, int lane"
+
+    @property
+    def chunk_args(self) -> str:
+        return "cfg, lane, gauge" if self.hook else "cfg, lane"
+
+    def slot_helicities(self) -> list:
+        """Helicity bit pattern (bit i set: leg i at +1) of every evaluated configuration, in the
+        order the kernels loop over them: pattern by pattern, gluon configurations in cfg order."""
+        proc = self.proc
+        out = []
+        for pat in self.pats:
+            for cfg in range(pat.ncfg):
+                lam = {0: 1}
+                lam.update({g: (1 if (cfg >> j) & 1 else -1) for j, g in enumerate(pat.free_gluons)})
+                lam.update(pat.fixed)
+                for q, hq in pat.hq.items():
+                    lam[q] = hq if proc.legs[q].flavour == "u" else -hq
+                out.append(sum(1 << i for i in range(proc.n) if lam[i] == 1))
+        return out
+
+    def reduction_matrix(self) -> list:
+        """Exact K' x K matrix M with y = M J: the reduced colour vector the kernels accumulate,
+        in terms of the colour-basis amplitudes of eq. (color-amplitude)."""
+        cs = self.cs
+        m = [[Fraction(0)] * self.k for _ in range(self.kdim)]
+        if cs.subst is None:
+            for a, p in enumerate(cs.pivots):
+                m[a][p] += 1
+            return m
+        sel, rmat = cs.subst
+        for a, s in enumerate(sel):
+            m[a][cs.pivots[s]] += 1
+        for b, row in rmat.items():
+            for a, r in enumerate(row):
+                if r != 0:
+                    m[a][cs.pivots[b]] += r
+        return m
 
     def lds_bytes(self, nwave: int) -> int:
         """Static LDS of one workgroup: momenta and colour vector of 64 events (+ partial sums)."""
@@ -442,8 +496,7 @@ class Emitter:
                         lam = str(pat.fixed[leg.index])
                     else:
                         lam = f"((cfg >> {pat.free_gluons.index(leg.index)}) & 1 ? 1 : -1)"
-                    w(f"  const vec4<R> w{leg.index} = vxxxx0<R>(pl{leg.index}, {lam}, "
-                      f"{'false' if leg.incoming else 'true'});")
+                    w(f"  const vec4<R> w{leg.index} = {self.gluon_ext(f'pl{leg.index}', lam, leg)};")
                 elif leg.kind == "I":
                     w(f"  const wsp<R> w{leg.index} = ixxxx0<R, {h[leg.index]}>(pl{leg.index});")
                 else:
@@ -474,7 +527,7 @@ class Emitter:
                         else:
                             w(f"  yl[{a}][0][lane] += {_lit(sc)} * k{ci}.re; yl[{a}][1][lane] += {_lit(sc)} * k{ci}.im;")
             name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_c{ki}"
-            src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+            src = (f"__device__ __noinline__ void {name}({self.chunk_params}) {{\n  using R = {prec};\n"
                    + "\n".join(lines) + "\n}\n")
             out.append([name, src, 0, flops, lines])
             total_flops += flops
@@ -500,7 +553,7 @@ class Emitter:
                         body.append("  {")
                         body.extend(c[4])
                         body.append("  }")
-                    src = (f"__device__ __noinline__ void {name}(int cfg, int lane) {{\n  using R = {prec};\n"
+                    src = (f"__device__ __noinline__ void {name}({self.chunk_params}) {{\n  using R = {prec};\n"
                            + "\n".join(body) + "\n}\n")
                     merged.append([name, src, v, sum(c[3] for c in run), body])
             out = merged
@@ -579,12 +632,16 @@ class Emitter:
         return out
 
     def _kernel(self, prec: str, chunks_per_pattern, sampled: bool = False) -> list:
-        """The summed kernel me2_* (every helicity configuration), or with sampled=True the kernel
-        me2h_* that evaluates one given helicity configuration per event."""
+        """The summed kernel me2_* (every helicity configuration), with sampled=True the kernel
+        me2h_* that evaluates one given helicity configuration per event, or, for a hook emitter,
+        the test-hook kernel me2x_* (summed, with the gauge substitution and the colour-vector
+        export)."""
         sfx = "f64" if prec == "double" else "f32"
         hel_arg = "const int* __restrict__ hel, const int* __restrict__ perm, " if sampled else ""
         args = (f"const double* __restrict__ mom, {hel_arg}int64_t nev, double* __restrict__ out, "
                 "const double* __restrict__ cmat, double scale")
+        if self.hook:
+            args += ", int gauge, double* __restrict__ jamp"
         nwave = self.nwave[prec]
         nt = 64 * nwave
         out = []
@@ -593,7 +650,8 @@ class Emitter:
         # chunk functions it calls) stays within the occupancy the LDS allows
         lds_waves_per_simd = (LDS_PER_CU // self.lds_bytes(nwave)) * nwave // 4
         min_waves = max(1, min(self.target_waves[prec] // 4, lds_waves_per_simd))
-        w(f"__global__ __launch_bounds__({nt}, {min_waves}) void me2{'h' if sampled else ''}_{sfx}({args}) {{")
+        kname = "me2x" if self.hook else ("me2h" if sampled else "me2")
+        w(f"__global__ __launch_bounds__({nt}, {min_waves}) void {kname}_{sfx}({args}) {{")
         w("  const int lane = threadIdx.x & 63;")
         w("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
         if sampled:
@@ -625,6 +683,8 @@ class Emitter:
             w("  const int my_pat = hcode >= 0 ? hcode >> 16 : -1;")
             w("  const int my_cfg = hcode >= 0 ? hcode & 0xffff : 0;")
         w("  double q = 0.0;")
+        slot0 = 0
+        nslots = sum(p.ncfg for p in self.pats)
         for pi, (pat, chunks) in enumerate(zip(self.pats, chunks_per_pattern)):
             if sampled:
                 w(f"  if (__syncthreads_or(my_pat == {pi})) {{")
@@ -641,10 +701,19 @@ class Emitter:
                 if nwave > 1:
                     w(f"    if (wave == {v}) {{")
                 for nm in names:
-                    w(f"      {nm}(cfg, lane);")
+                    w(f"      {nm}({self.chunk_args});")
                 if nwave > 1:
                     w("    }")
             w("    __syncthreads();")
+            if self.hook:
+                # reduced colour vector of this configuration: jamp[ev][slot][a][re, im]
+                w("    if (jamp != nullptr && ev < nev) {")
+                w(f"      double* dst = jamp + ((size_t)ev * {nslots} + {slot0} + cfg) * {2 * self.kdim};")
+                w(f"      for (int a = wave; a < {self.kdim}; a += {nwave}) {{")
+                w("        dst[2 * a] = yl[a][0][lane];")
+                w("        dst[2 * a + 1] = yl[a][1][lane];")
+                w("      }")
+                w("    }")
             part = f"colour_sum_lds_part<{self.kdim}, {self.cblock}, {nwave}>(yl, lane, wave, cmat)"
             if sampled:
                 w(f"    const double part = {part};")
@@ -653,6 +722,7 @@ class Emitter:
                 w(f"    q += {part};")
             w("    __syncthreads();")
             w("  }")
+            slot0 += pat.ncfg
         res = "(hcode == -2 ? __builtin_nan(\"\") : t * scale)" if sampled else "t * scale"
         if nwave > 1:
             w(f"  __shared__ double qsum[{nwave}][64];")
@@ -669,15 +739,13 @@ class Emitter:
         w("}")
         return out
 
-    def emit(self) -> dict:
-        """Sources of one process: {"f64": float64 kernels + host descriptor, "f32": mixed kernels}.
+    def max_launch_events(self) -> int:
+        """Events one launch may cover: the grid's x dimension times the workgroup size must stay
+        below 2^32 work-items, and a workgroup owns 64 events."""
+        return ((1 << 32) - 1) // (64 * max(self.nwave.values())) * 64
 
-        The two precisions share no device code, so they are separate translation units that
-        compile in parallel; the host part launches the mixed kernels through declarations."""
+    def _head(self) -> list:
         proc, dag = self.proc, self.dag
-        ns = f"p_{proc.tag}"
-        chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
-                  for prec in ("double", "float")}
         head = [f"// Generated by paper_0909_5257_amd.gen for the process \"{proc.spec}\".  Do not edit.",
                 f"// diagrams {len(dag.amps)}, shared currents {len(dag.nodes) - proc.n}, colour basis {self.k}, "
                 f"reduced colour space {self.kdim}, helicity patterns {len(self.pats)}, "
@@ -688,20 +756,80 @@ class Emitter:
                 head.append(f"// {prec} pattern {s['pattern']}: {s['amps']} amplitudes in {s['groups']} groups and "
                             f"{s['chunks']} chunks, {s['node_evals']} current evaluations, peak {s['max_peak']} "
                             f"registers (simulated), flops per wave {s['wave_flops']}")
+        return head
+
+    def _device_prelude(self, ns: str, with_hmap: bool) -> list:
+        proc = self.proc
+        lines = ['#include "heget_device.hpp"', '#include "heget_kernel_common.hpp"', "",
+                 "namespace heget {", f"namespace {ns} {{", f"constexpr int NEXT = {proc.n};", "namespace {",
+                 "__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events",
+                 f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event"]
+        if with_hmap:
+            lines.append(f"__constant__ int HMAP[{1 << proc.n}] = {{"
+                         + ", ".join(str(x) for x in self.helicity_map()) + "};")
+        return lines
+
+    def emit_hook(self) -> str:
+        """The test-hook translation unit: me2x_f64 and me2x_f32 with their own chunk functions,
+        and the host launcher launch_hook_<tag> (events in slices that fit one launch)."""
+        assert self.hook
+        proc = self.proc
+        ns = f"p_{proc.tag}_hook"
+        chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
+                  for prec in ("double", "float")}
+        lines = self._head() + ["// test-hook kernels: gauge substitution and colour-vector export"]
+        lines += self._device_prelude(ns, with_hmap=False)
+        for prec in ("double", "float"):
+            for pat_chunks in chunks[prec]:
+                for c in pat_chunks:
+                    lines.append(c[1])
+        lines.append("}  // namespace")
+        for prec in ("double", "float"):
+            lines.extend(self._kernel(prec, chunks[prec]))
+        lines += [f"}}  // namespace {ns}", "}  // namespace heget", ""]
+        nslots = sum(p.ncfg for p in self.pats)
+        per = self.max_launch_events()
+        w = lines.append
+        w("#if !defined(__HIP_DEVICE_COMPILE__)")
+        w(f"hipError_t launch_hook_{proc.tag}(int prec, const double* mom, int64_t n, double* out, "
+          "const double* cmat, double scale, int gauge, double* jamp, hipStream_t s) {")
+        w(f"  for (int64_t off = 0; off < n; off += {per}LL) {{")
+        w(f"    const int64_t m = n - off < {per}LL ? n - off : {per}LL;")
+        w(f"    const dim3 grid((unsigned)((m + 63) / 64)), "
+          f"block(prec == 0 ? {64 * self.nwave['double']} : {64 * self.nwave['float']});")
+        w(f"    const double* mo = mom + off * {4 * proc.n};")
+        w(f"    double* jo = jamp ? jamp + off * {nslots * 2 * self.kdim}LL : nullptr;")
+        w("    if (prec == 0)")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2x_f64, grid, block, 0, s, mo, m, out + off, cmat, scale, "
+          "gauge, jo);")
+        w("    else")
+        w(f"      hipLaunchKernelGGL(heget::{ns}::me2x_f32, grid, block, 0, s, mo, m, out + off, cmat, scale, "
+          "gauge, jo);")
+        w("    const hipError_t e = hipGetLastError();")
+        w("    if (e != hipSuccess) return e;")
+        w("  }")
+        w("  return hipSuccess;")
+        w("}")
+        w("#endif")
+        return "\n".join(lines) + "\n"
+
+    def emit(self, with_hook: bool = False) -> dict:
+        """Sources of one process: {"f64": float64 kernels + host descriptor, "f32": mixed kernels}.
+
+        The two precisions share no device code, so they are separate translation units that
+        compile in parallel; the host part launches the mixed kernels through declarations.
+        with_hook: the descriptor points at launch_hook_<tag> from the separate test-hook unit."""
+        assert not self.hook
+        proc, dag = self.proc, self.dag
+        ns = f"p_{proc.tag}"
+        chunks = {prec: [self.emit_pattern(i, p, prec) for i, p in enumerate(self.pats)]
+                  for prec in ("double", "float")}
+        head = self._head()
         out = {}
         for prec in ("double", "float"):
             lines = list(head)
             w = lines.append
-            w('#include "heget_device.hpp"')
-            w('#include "heget_kernel_common.hpp"')
-            w("")
-            w("namespace heget {")
-            w(f"namespace {ns} {{")
-            w(f"constexpr int NEXT = {proc.n};")
-            w("namespace {")
-            w(f"__shared__ double pml[NEXT][4][64];        // per-event momenta of the workgroup's 64 events")
-            w(f"__shared__ double yl[{self.kdim}][2][64];  // reduced colour vector per event")
-            w(f"__constant__ int HMAP[{1 << proc.n}] = {{" + ", ".join(str(x) for x in self.helicity_map()) + "};")
+            lines += self._device_prelude(ns, with_hmap=True)
             for pat_chunks in chunks[prec]:
                 for c in pat_chunks:
                     lines.append(c[1])
@@ -733,33 +861,66 @@ class Emitter:
                  for a in range(self.k) for b in range(self.k)]
         w(f"static const long long k_num_{proc.tag}[] = {{" + ", ".join(str(x[0]) for x in nvals) + "};")
         w(f"static const long long k_den_{proc.tag}[] = {{" + ", ".join(str(x[1]) for x in nvals) + "};")
+        # exact reduction map y = M J and reduced colour matrix W (Q = y^H W y), for the test hooks
+        mred = [x for row in self.reduction_matrix() for x in row]
+        wred = [x for row in self.cs.w for x in row]
+        for name, vals in (("red", mred), ("w", wred)):
+            assert all(abs(x.numerator) < (1 << 62) and x.denominator < (1 << 62) for x in vals)
+            w(f"static const long long k_{name}_num_{proc.tag}[] = {{" + ", ".join(str(x.numerator) for x in vals) + "};")
+            w(f"static const long long k_{name}_den_{proc.tag}[] = {{" + ", ".join(str(x.denominator) for x in vals)
+              + "};")
+        slots = self.slot_helicities()
+        w(f"static const int k_slot_hel_{proc.tag}[] = {{" + ", ".join(str(x) for x in slots) + "};")
+        per = self.max_launch_events()
         w(f"static hipError_t launch_{proc.tag}(int prec, const double* mom, const int* hel, const int* perm, "
           f"int64_t n, double* out, const double* cmat, double scale, hipStream_t s) {{")
-        w(f"  const dim3 grid((unsigned)((n + 63) / 64)), "
+        w(f"  // events in slices of at most {per} (2^32 work-items per grid dimension); a permutation")
+        w("  // (sampled mode, events sorted by pattern) indexes the whole batch and needs one slice")
+        w(f"  if (perm != nullptr && n > {per}LL) return hipErrorInvalidValue;")
+        w(f"  for (int64_t off = 0; off < n; off += {per}LL) {{")
+        w(f"    const int64_t m = n - off < {per}LL ? n - off : {per}LL;")
+        w(f"    const dim3 grid((unsigned)((m + 63) / 64)), "
           f"block(prec == 0 ? {64 * self.nwave['double']} : {64 * self.nwave['float']});")
-        w("  if (hel == nullptr) {")
-        w("    if (prec == 0)")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2_f64, grid, block, 0, s, mom, n, out, cmat, scale);")
-        w("    else")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mom, n, out, cmat, scale);")
-        w("  } else {")
-        w("    if (prec == 0)")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
-        w("    else")
-        w(f"      hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
+        w(f"    const double* mo = mom + off * {4 * proc.n};")
+        w("    if (hel == nullptr) {")
+        w("      if (prec == 0)")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2_f64, grid, block, 0, s, mo, m, out + off, cmat, scale);")
+        w("      else")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2_f32, grid, block, 0, s, mo, m, out + off, cmat, scale);")
+        w("    } else if (perm == nullptr) {")
+        w("      if (prec == 0)")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mo, hel + off, perm, m, out + off, "
+          "cmat, scale);")
+        w("      else")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mo, hel + off, perm, m, out + off, "
+          "cmat, scale);")
+        w("    } else {")
+        w("      if (prec == 0)")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2h_f64, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
+        w("      else")
+        w(f"        hipLaunchKernelGGL(heget::{ns}::me2h_f32, grid, block, 0, s, mom, hel, perm, n, out, cmat, scale);")
+        w("    }")
+        w("    const hipError_t e = hipGetLastError();")
+        w("    if (e != hipSuccess) return e;")
         w("  }")
-        w("  return hipGetLastError();")
+        w("  return hipSuccess;")
         w("}")
+        if with_hook:
+            w(f"hipError_t launch_hook_{proc.tag}(int prec, const double* mom, int64_t n, double* out, "
+              "const double* cmat, double scale, int gauge, double* jamp, hipStream_t s);")
         nhel = 2 * sum(p.ncfg for p in self.pats)
         hmap = self.helicity_map()
         pat_of = [hmap[h if h & 1 else ~h & ((1 << proc.n) - 1)] for h in range(1 << proc.n)]
         w(f"static const int k_pattern_{proc.tag}[] = {{" + ", ".join(str(c >> 16 if c >= 0 else -1) for c in pat_of)
           + "};")
-        w(f"extern const heget_proc_desc heget_desc_{proc.tag} = {{")
+        t = proc.tag
+        w(f"extern const heget_proc_desc heget_desc_{t} = {{")
         w(f"  \"{proc.spec}\", {proc.n}, {len(dag.amps)}, {self.k}, {nhel}, {1 << proc.n},")
-        w(f"  {len(table)}, k_colour_table_{proc.tag}, k_num_{proc.tag}, k_den_{proc.tag},")
-        w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{proc.tag},")
-        w(f"  {len(self.pats)}, k_pattern_{proc.tag}}};")
+        w(f"  {len(table)}, k_colour_table_{t}, k_num_{t}, k_den_{t},")
+        w(f"  {{{self.flops['double']}LL, {self.flops['float']}LL}}, {self.algo_flops}LL, launch_{t},")
+        w(f"  {len(self.pats)}, k_pattern_{t},")
+        w(f"  {self.kdim}, {len(slots)}, k_slot_hel_{t}, k_red_num_{t}, k_red_den_{t}, k_w_num_{t}, k_w_den_{t},")
+        w(f"  {'launch_hook_' + t if with_hook else 'nullptr'}, {per}LL}};")
         w("#endif")
         out["f64"] = "\n".join(lines) + "\n"
         return out

@@ -75,6 +75,10 @@ def lib():
     L.heget_apply_cuts.restype = i32
     L.heget_integrate_step.argtypes = [vp, i64, vp, vp, vp, dbl, ctypes.POINTER(Cuts), vp, vp, vp, vp, vp]
     L.heget_integrate_step.restype = i32
+    L.heget_colour_reduction.argtypes = [vp, pi32, pi32, pi64, pi64, pi64, pi64, pi32]
+    L.heget_colour_reduction.restype = i32
+    L.heget_matrix_elements_hook.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
+    L.heget_matrix_elements_hook.restype = i32
     L.heget_num_processes.argtypes = []
     L.heget_num_processes.restype = i32
     L.heget_process_spec.argtypes = [i32]
@@ -91,6 +95,41 @@ def _check(status, what):
 def supported_processes() -> list:
     L = lib()
     return [L.heget_process_spec(i).decode() for i in range(L.heget_num_processes())]
+
+
+def _launch_stream(device, stream):
+    """The stream to launch on.  A caller-given stream other than the current one first waits for
+    the current stream, so that buffers prepared there (copies, allocations) are ready."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if stream is None:
+        return cur, False
+    if stream != cur:
+        stream.wait_stream(cur)
+        return stream, True
+    return stream, False
+
+
+def _keep_alive(side_stream: bool, stream, *tensors):
+    """Tell the caching allocator that temporaries are used on a side stream (no reuse before the
+    work queued there has run)."""
+    if side_stream:
+        for t in tensors:
+            t.record_stream(stream)
+
+
+def _check_out(out, n, device):
+    import torch
+    if out.dtype != torch.float64 or out.device != device or not out.is_contiguous() or tuple(out.shape) != (n,):
+        raise TypeError(f"out must be a contiguous float64 tensor of shape ({n},) on {device}")
+
+
+def _check_momenta(momenta, n_ext):
+    import torch
+    if momenta.dtype != torch.float64 or not momenta.is_cuda:
+        raise TypeError("momenta must be a float64 tensor on the GPU")
+    if momenta.dim() != 3 or momenta.shape[1:] != (n_ext, 4):
+        raise ValueError(f"momenta must have shape [N, {n_ext}, 4]")
 
 
 class Process:
@@ -146,40 +185,80 @@ class Process:
     def matrix_elements(self, momenta, alpha_s: float, out=None, stream=None):
         """|M|^2 for a device tensor of momenta [N, n_ext, 4] float64 (torch, on the GPU)."""
         import torch
-        if momenta.dtype != torch.float64 or not momenta.is_cuda:
-            raise TypeError("momenta must be a float64 tensor on the GPU")
-        if momenta.dim() != 3 or momenta.shape[1:] != (self.n_ext, 4):
-            raise ValueError(f"momenta must have shape [N, {self.n_ext}, 4]")
+        _check_momenta(momenta, self.n_ext)
         momenta = momenta.contiguous()
         n = momenta.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=momenta.device)
-        if stream is None:
-            stream = torch.cuda.current_stream(momenta.device)
+        _check_out(out, n, momenta.device)
+        stream, side = _launch_stream(momenta.device, stream)
         self.matrix_elements_ptr(momenta.data_ptr(), n, alpha_s, out.data_ptr(), stream.cuda_stream)
+        _keep_alive(side, stream, momenta, out)
         return out
 
     def matrix_elements_helicity(self, momenta, helicity, alpha_s: float, out=None, stream=None):
         """One helicity term per event: helicity is an int32 device tensor [N] of bit patterns."""
         import torch
-        if momenta.dtype != torch.float64 or not momenta.is_cuda:
-            raise TypeError("momenta must be a float64 tensor on the GPU")
-        if momenta.dim() != 3 or momenta.shape[1:] != (self.n_ext, 4):
-            raise ValueError(f"momenta must have shape [N, {self.n_ext}, 4]")
+        _check_momenta(momenta, self.n_ext)
         if helicity.dtype != torch.int32 or not helicity.is_cuda or helicity.shape != momenta.shape[:1]:
             raise TypeError("helicity must be an int32 GPU tensor [N]")
         momenta, helicity = momenta.contiguous(), helicity.contiguous()
         n = momenta.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=momenta.device)
-        if stream is None:
-            stream = torch.cuda.current_stream(momenta.device)
+        _check_out(out, n, momenta.device)
+        stream, side = _launch_stream(momenta.device, stream)
         _check(lib().heget_matrix_elements_helicity(self._h, ctypes.c_void_p(momenta.data_ptr()),
                                                     ctypes.c_void_p(helicity.data_ptr()), n, alpha_s,
                                                     ctypes.c_void_p(out.data_ptr()),
                                                     ctypes.c_void_p(stream.cuda_stream)),
                "heget_matrix_elements_helicity")
+        _keep_alive(side, stream, momenta, helicity, out)
         return out
+
+    def colour_reduction(self):
+        """(M, W, slot_helicity): exact y = M J (Fractions, [K', K]), Q = y^H W y ([K', K']) and the
+        helicity bit pattern of every evaluated configuration (the jamp slots of matrix_elements_hook)."""
+        from fractions import Fraction
+        kr, ns = ctypes.c_int(), ctypes.c_int()
+        L = lib()
+        _check(L.heget_colour_reduction(self._h, ctypes.byref(kr), ctypes.byref(ns), None, None, None, None, None),
+               "heget_colour_reduction")
+        k, kr, ns = self.n_colours, kr.value, ns.value
+        mn, md = np.zeros(kr * k, np.int64), np.zeros(kr * k, np.int64)
+        wn, wd = np.zeros(kr * kr, np.int64), np.zeros(kr * kr, np.int64)
+        sh = np.zeros(ns, np.int32)
+        p64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(L.heget_colour_reduction(self._h, ctypes.byref(ctypes.c_int()), ctypes.byref(ctypes.c_int()),
+                                        p64(mn), p64(md), p64(wn), p64(wd),
+                                        sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+               "heget_colour_reduction")
+        m = [[Fraction(int(mn[a * k + b]), int(md[a * k + b])) for b in range(k)] for a in range(kr)]
+        w = [[Fraction(int(wn[a * kr + b]), int(wd[a * kr + b])) for b in range(kr)] for a in range(kr)]
+        return m, w, sh
+
+    def matrix_elements_hook(self, momenta, alpha_s: float, gauge_leg: int = -1, with_jamp: bool = False,
+                             stream=None):
+        """Test hook: (me2 [N], jamp [N, n_slots, K', 2] or None) through the test-hook kernels."""
+        import torch
+        _check_momenta(momenta, self.n_ext)
+        momenta = momenta.contiguous()
+        n = momenta.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        jamp = None
+        if with_jamp:
+            kr, ns = ctypes.c_int(), ctypes.c_int()
+            _check(lib().heget_colour_reduction(self._h, ctypes.byref(kr), ctypes.byref(ns), None, None, None, None,
+                                                None), "heget_colour_reduction")
+            jamp = torch.empty((n, ns.value, kr.value, 2), dtype=torch.float64, device=momenta.device)
+        stream, side = _launch_stream(momenta.device, stream)
+        _check(lib().heget_matrix_elements_hook(self._h, ctypes.c_void_p(momenta.data_ptr()), n, alpha_s,
+                                                gauge_leg, ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(None if jamp is None else jamp.data_ptr()),
+                                                ctypes.c_void_p(stream.cuda_stream)),
+               "heget_matrix_elements_hook")
+        _keep_alive(side, stream, momenta, out, *([] if jamp is None else [jamp]))
+        return out, jamp
 
 
 def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream=None):
@@ -189,8 +268,9 @@ def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream
     for i, (proc, mom, out) in enumerate(items):
         if mom.dtype != torch.float64 or not mom.is_cuda or not mom.is_contiguous():
             raise TypeError("momenta must be contiguous float64 GPU tensors")
-        if mom.dim() != 3 or mom.shape[1:] != (proc.n_ext, 4) or out.shape[0] != mom.shape[0]:
-            raise ValueError("bad momenta/output shape")
+        if mom.dim() != 3 or mom.shape[1:] != (proc.n_ext, 4):
+            raise ValueError("bad momenta shape")
+        _check_out(out, mom.shape[0], mom.device)
         arr[i] = BatchItem(proc.handle.value, mom.data_ptr(), mom.shape[0], out.data_ptr())
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -199,7 +279,7 @@ def matrix_elements_batch(items, alpha_s: float, use_graph: bool = False, stream
            "heget_matrix_elements_batch")
 
 
-COLOUR_MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+COLOUR_MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp64_valu": 3}
 
 
 def colour_quadratic_form(nmat, jamp, mode: str = "fp64", out=None, stream=None):

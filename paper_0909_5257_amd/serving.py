@@ -55,9 +55,10 @@ class Server:
     """Admission by HBM budget, a pool of streams, completion by events."""
 
     def __init__(self, specs, precisions=("mixed",), hbm_budget_bytes: int = 8 << 30,
-                 n_streams: int = 4, device: str = "cuda:0"):
+                 n_streams: int = 4, device: str = "cuda:0", alpha_s: float = 0.118):
         import torch
         self.torch = torch
+        self.alpha_s = alpha_s
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.in_use = 0
@@ -96,14 +97,23 @@ class Server:
             st = self.streams[si]
             self.in_use += req.device_bytes
             req.t_start = time.perf_counter()
-            with torch.cuda.stream(st):
-                mom = torch.from_numpy(req.momenta).pin_memory().to(self.device, non_blocking=True)
-                out = torch.empty(req.n, dtype=torch.float64, device=self.device)
-                self.procs[(req.spec, req.precision)].matrix_elements(mom, 0.118, out=out, stream=st)
-                host = torch.empty(req.n, dtype=torch.float64, pin_memory=True)
-                host.copy_(out, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(st)
+            try:
+                with torch.cuda.stream(st):
+                    mom = torch.from_numpy(req.momenta).pin_memory().to(self.device, non_blocking=True)
+                    out = torch.empty(req.n, dtype=torch.float64, device=self.device)
+                    self.procs[(req.spec, req.precision)].matrix_elements(mom, self.alpha_s, out=out, stream=st)
+                    host = torch.empty(req.n, dtype=torch.float64, pin_memory=True)
+                    host.copy_(out, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+            except Exception as exc:       # this request fails alone: give its slot and budget back
+                req.error = f"{type(exc).__name__}: {exc}"
+                req.t_done = time.perf_counter()
+                self.in_use -= req.device_bytes
+                self.free_streams.append(si)
+                self.completed.append(req)
+                req.done.set()
+                continue
             self.running.append((req, si, ev, (mom, out, host)))
 
     def _reap(self):

@@ -211,3 +211,33 @@ def test_committed_tuned_table_is_valid():
     for (spec, prec), s in TUNED.items():
         assert spec in PROCESSES and prec in ("double", "float")
         assert s.get("externals") in (None, "group") and 64 <= s.get("budget", 176) <= 512
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g", "g g > g g g g", "u u~ > g g g g", "u u > u u g", "u u > u u g g",
+                                  "u u~ > u u~"])
+def test_reduction_map_and_slot_table(spec):
+    """The exported map of the test hooks: the reduced vector the kernels accumulate is exactly
+    y = M J for any diagram amplitudes, and the slot table lists each evaluated helicity
+    configuration once, in the order the helicity map gives them."""
+    dag = Dag(parse(spec))
+    em = Emitter(dag, dag.colour_matrix())
+    m = np.array([[float(x) for x in row] for row in em.reduction_matrix()])
+    rng = np.random.default_rng(8)
+    k = len(dag.basis)
+    amp = rng.normal(size=len(dag.amps)) + 1j * rng.normal(size=len(dag.amps))
+    jv = np.zeros(k, complex)
+    yv = np.zeros(em.kdim, complex)
+    for i, a in enumerate(dag.amps):
+        for idx, v in a.coef.items():
+            jv[idx] += v * amp[i]
+        for idx, v in em.cs.vector(a.coef).items():
+            yv[idx] += float(v) * amp[i]
+    assert np.allclose(m @ jv, yv, rtol=0, atol=1e-12 * np.abs(yv).max())
+    slots = em.slot_helicities()
+    hmap = em.helicity_map()
+    assert len(slots) == len(set(slots)) == sum(p.ncfg for p in em.pats)
+    offsets = np.cumsum([0] + [p.ncfg for p in em.pats])
+    for s, h in enumerate(slots):
+        assert h & 1                                  # leg 0 at +1
+        pi = int(np.searchsorted(offsets, s, side="right") - 1)
+        assert hmap[h] == (pi << 16) | (s - offsets[pi])

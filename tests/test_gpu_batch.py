@@ -72,3 +72,53 @@ def test_batch_graph_replays(torch_dev):
         torch.cuda.synchronize()
         for (spec, _), r, o in zip(inputs, ref, outs):
             _same(spec, r, o, f"replay {rep}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_c4_batch_against_oracle(torch_dev, precision):
+    """The fused uneven batch of the C4 configuration (eight processes, 2^U[10,20] events each from
+    seed 7, about 1.6 M events), eager and as a replayed graph, against stored oracle values of 64
+    sampled events per process (tests/golden/oracle_fused_c4_<i>.txt)."""
+    torch = torch_dev
+    from conftest import load_oracle_sample, rel_err_summary, sample_events
+    from paper_0909_5257_amd.heget import Process, matrix_elements_batch
+    samples = [load_oracle_sample(f"fused_c4_{i}") for i in range(len(FUSED))]
+    assert [s["spec"] for s in samples] == FUSED
+    xs = [torch.from_numpy(sample_events(s)).to("cuda") for s in samples]
+    procs = [Process(s["spec"], precision) for s in samples]
+    outs = [torch.empty(x.shape[0], dtype=torch.float64, device="cuda") for x in xs]
+    items = list(zip(procs, xs, outs))
+    for graph in (False, True, True):
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        matrix_elements_batch(items, 0.118, use_graph=graph)
+        torch.cuda.synchronize()
+        for s, o in zip(samples, outs):
+            got = o.cpu().numpy()
+            assert np.all(np.isfinite(got)) and np.all(got > 0), s["spec"]
+            err = rel_err_summary(got[s["idx"]], s["me2"])
+            print(f"[fused c4] {precision} graph={graph} {s['spec']} ({s['n']} events): max rel err "
+                  f"{err['max']:.3e}, p99 {err['p99']:.3e}, median {err['median']:.3e}", flush=True)
+            assert err["max"] <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_graph_cache_after_handle_reuse(torch_dev):
+    """A cached batch graph must not survive its handle: destroy a handle after a graph replay and
+    create one of the other precision (the allocator tends to hand back the same addresses); the
+    next graph call on the same buffers must run the new handle's kernels."""
+    torch = torch_dev
+    from paper_0909_5257_amd.heget import Process, matrix_elements_batch
+    spec = "u u~ > g g g"
+    x = torch.from_numpy(generate_events(3000, 3, KIN_C2, seed=12)).to("cuda")
+    out = torch.empty(3000, dtype=torch.float64, device="cuda")
+    ref = {}
+    for precision in ("mixed", "fp64"):
+        p = Process(spec, precision)
+        ref[precision] = p.matrix_elements(x, 0.118).clone()
+        matrix_elements_batch([(p, x, out)], 0.118, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref[precision]), precision
+        del p
+    # the two precisions differ, so a stale graph would have been caught above
+    assert not torch.equal(ref["mixed"], ref["fp64"])

@@ -40,14 +40,16 @@ def torch_dev():
 
 @pytest.fixture(scope="module")
 def reference():
-    """Oracle values for a small ragged batch and for sampled events of a 2^16 batch."""
+    """Oracle values for a small ragged batch (computed here) and for 64 sampled events of the
+    benchmark's 2^18-event batch (stored: tests/golden/oracle_gg_ggggg_c2_2e18.txt)."""
+    from conftest import load_oracle_sample, sample_events
     from oracle.berends_giele import bg_amplitudes, bg_me2, trace_colour_matrix
     from oracle.me2 import helicity_table
     small = generate_events(70, 5, KIN_C2, seed=0, stream=5)
-    big = generate_events(1 << 16, 5, KIN_C2, seed=1, stream=5)
-    idx = np.linspace(0, (1 << 16) - 1, 6).astype(int)
+    stored = load_oracle_sample("gg_ggggg_c2_2e18")
+    big = sample_events(stored)
+    idx, ref_big = stored["idx"], stored["me2"]
     ref_small = bg_me2(SPEC, small[:6], ALPHA_S)
-    ref_big = bg_me2(SPEC, big[idx], ALPHA_S)
     # per-helicity terms of the first events for the sampled mode
     words, nmat = trace_colour_matrix(7)
     amps = bg_amplitudes(SPEC, small[:6], helicity_table(7))
@@ -69,11 +71,12 @@ def test_gg_5g_parity(torch_dev, reference, precision):
     got = proc.matrix_elements(torch.from_numpy(small).to("cuda"), ALPHA_S).cpu().numpy()
     rel = np.abs(got[:6] / ref_small - 1.0)
     assert np.all(np.isfinite(got)) and np.all(got > 0)
-    _say(f"[gg5g] {precision}: 65536 events")
+    _say(f"[gg5g] {precision}: {big.shape[0]} events")
     got_big = proc.matrix_elements(torch.from_numpy(big).to("cuda"), ALPHA_S).cpu().numpy()
     torch.cuda.synchronize()
     rel_big = np.abs(got_big[idx] / ref_big - 1.0)
-    _say(f"[gg5g] {precision}: max rel err {max(rel.max(), rel_big.max()):.3e}")
+    _say(f"[gg5g] {precision}: max rel err {max(rel.max(), rel_big.max()):.3e} ({len(idx)} sampled of "
+         f"{big.shape[0]}: p99 {np.percentile(rel_big, 99):.3e}, median {np.median(rel_big):.3e})")
     assert rel.max() <= TOL[precision] and rel_big.max() <= TOL[precision]
     assert np.all(np.isfinite(got_big))
 

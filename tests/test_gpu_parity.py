@@ -75,27 +75,37 @@ def test_parity_small(torch_dev, spec, n, precision):
     assert rel.max() <= TOL[precision]
 
 
-@pytest.mark.parametrize("spec,n_full,n_sample", [
-    ("g g > g g", 65536, 64),
-    ("u u~ > g g g g", 1 << 20, 16),
-    ("u u > u u g g", 1 << 20, 16),
-    ("g g > g g g g", 1 << 21, 16),
-    ("u u~ > g g g g g", 1 << 20, 8),
-    ("u u > u u g g g", 1 << 18, 6),
-])
-def test_parity_full_size_sampled(torch_dev, spec, n_full, n_sample):
-    """Workload-size launches, compared with the oracle on sampled events."""
-    kin = KIN_C1 if _nfinal(spec) == 2 else KIN_C2
-    p = generate_events(n_full, _nfinal(spec), kin, seed=0)
-    idx = np.random.default_rng(1).choice(n_full, n_sample, replace=False)
-    ref = _oracle(spec, p[idx])
+# stored oracle samples (tests/golden/oracle_<name>.txt): 512 sampled events of each workload-size
+# launch (C1, C2, C3 and the metric's u u~ > 5g), and of the serving pools at C5 kinematics
+FULL_SIZE = ["gg_gg_c1_65536", "uux_gggg_c2_2e20", "uu_uugg_c2_2e20", "gg_gggg_c2_2e21",
+             "uux_ggggg_c2_2e20", "uu_uuggg_c2_2e18"]
+SERVING_C5 = ["gg_ggg_c5_2e18", "gg_gggg_c5_2e18", "uux_ggggg_c5_2e18", "uu_uuggg_c5_2e18"]
+
+
+def _sampled_parity(torch, name):
+    from conftest import load_oracle_sample, rel_err_summary, sample_events
+    s = load_oracle_sample(name)
+    p = sample_events(s)
     for precision in ("fp64", "mixed"):
-        _say(f"[full] {spec} {precision} n={n_full}")
-        got = _run(torch_dev, spec, precision, p)
+        _say(f"[sampled] {name} {s['spec']} {precision} n={s['n']}")
+        got = _run(torch, s["spec"], precision, p)
         assert np.all(np.isfinite(got)) and np.all(got > 0)
-        rel = np.abs(got[idx] / ref - 1.0)
-        _say(f"[full] {spec} {precision}: sampled max rel err {rel.max():.3e}")
-        assert rel.max() <= TOL[precision]
+        err = rel_err_summary(got[s["idx"]], s["me2"])
+        _say(f"[sampled] {name} {precision}: rel err vs oracle over {err['n']} events: max {err['max']:.3e}, "
+             f"p99 {err['p99']:.3e}, median {err['median']:.3e}")
+        assert err["max"] <= TOL[precision]
+
+
+@pytest.mark.parametrize("name", FULL_SIZE)
+def test_parity_full_size_sampled(torch_dev, name):
+    """Workload-size launches, compared with the oracle on 512 sampled events, both precisions."""
+    _sampled_parity(torch_dev, name)
+
+
+@pytest.mark.parametrize("name", SERVING_C5)
+def test_parity_serving_kinematics(torch_dev, name):
+    """The serving workload's kinematics (sqrt(s) up to 3 TeV) at 2^18 events, 512 sampled."""
+    _sampled_parity(torch_dev, name)
 
 
 def test_batch_independence_and_ragged_sizes(torch_dev):

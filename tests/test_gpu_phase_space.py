@@ -82,11 +82,15 @@ def test_cuts_parity(torch_dev, nf, dr):
     assert np.array_equal(got[~tie].astype(bool), ref[~tie])
 
 
-@pytest.mark.parametrize("spec,n,sampled", [
-    ("g g > g g", 3000, False), ("g g > g g g", 1000, False), ("u u~ > g g g g", 300, False),
-    ("u u > u u g", 1000, False), ("g g > g g g", 1000, True), ("u u > u u g g", 200, True),
+@pytest.mark.parametrize("spec,n,sampled,precision", [
+    ("g g > g g", 3000, False, "fp64"), ("g g > g g g", 1000, False, "fp64"), ("u u~ > g g g g", 300, False, "fp64"),
+    ("u u > u u g", 1000, False, "fp64"), ("g g > g g g", 1000, True, "fp64"), ("u u > u u g g", 200, True, "fp64"),
+    ("g g > g g g g", 300, False, "mixed"), ("g g > g g g", 1000, False, "mixed"),
+    ("u u > u u g g", 200, True, "mixed"), ("g g > g g g g", 300, True, "mixed"),
 ])
-def test_integrate_step_parity(torch_dev, spec, n, sampled):
+def test_integrate_step_parity(torch_dev, spec, n, sampled, precision):
+    """Against the oracle's RAMBO, |M|^2 and weights on the same uniforms: 1e-11 (float64, relative to
+    |M|^2 times the RAMBO conditioning factor) and 1e-5 (mixed)."""
     from oracle import oracle_me2
     from oracle import phase_space as ops
     from paper_0909_5257_amd import heget
@@ -96,15 +100,21 @@ def test_integrate_step_parity(torch_dev, spec, n, sampled):
     dr = 0.0 if nf == 2 else CUTS[2]
     rs, u = rambo_uniforms(n, nf, kin, seed=7)
     hel = random_helicities(n, nf + 2, seed=7) if sampled else None
-    _say(f"[integrate] {spec} n={n} sampled={sampled}")
-    proc = heget.Process(spec, "fp64")
+    _say(f"[integrate] {spec} {precision} n={n} sampled={sampled}")
+    proc = heget.Process(spec, precision)
+    tol = 1e-11 if precision == "fp64" else 1e-5
     out = heget.integrate_step(proc, _cuda(torch, rs), _cuda(torch, u), ALPHA_S, CUTS[0], CUTS[1], dr,
                                helicity=None if hel is None else _cuda(torch, hel))
     mom, me2, w, sums = (t.cpu().numpy() for t in out)
     again = heget.integrate_step(proc, _cuda(torch, rs), _cuda(torch, u), ALPHA_S, CUTS[0], CUTS[1], dr,
                                  helicity=None if hel is None else _cuda(torch, hel))[3].cpu().numpy()
     torch.cuda.synchronize()
-    assert np.array_equal(sums, again)
+    from conftest import cooperative_processes
+    if spec in cooperative_processes():
+        # several waves add into one colour vector with float64 LDS atomics in run-dependent order
+        assert np.max(np.abs(again / sums - 1.0)) < 1e-13
+    else:
+        assert np.array_equal(sums, again)
 
     ref_mom, _ = ops.rambo(rs, u)
     k = np.maximum(1.0, ops.rambo_gamma(u) ** 2)
@@ -123,11 +133,11 @@ def test_integrate_step_parity(torch_dev, spec, n, sampled):
     assert not tie.any()
     err = np.abs(me2 - ref_me2) / (scale * k)
     _say(f"[integrate] {spec}: max |d me2| / (k |M|^2) = {err.max():.2e}")
-    assert err.max() <= 1e-11
+    assert err.max() <= tol
     passed = ref_f != 0
     assert np.array_equal(w != 0, passed)
-    assert np.all(np.abs(w - ref_f)[passed] <= 1e-11 * (k * f_scale)[passed])
-    np.testing.assert_allclose(sums, [ref_f.sum(), (ref_f ** 2).sum()], rtol=1e-10)
+    assert np.all(np.abs(w - ref_f)[passed] <= tol * (k * f_scale)[passed])
+    np.testing.assert_allclose(sums, [ref_f.sum(), (ref_f ** 2).sum()], rtol=10 * tol)
     mean = sums[0] / n
     err = np.sqrt(max(sums[1] / n - mean * mean, 0.0) / (n - 1))
     _say(f"[integrate] {spec}: sigma-hat = {mean:.6g} +- {err:.2g} pb, pass {passed.mean():.3f}")
