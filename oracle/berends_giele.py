@@ -1,4 +1,4 @@
-"""Colour-ordered Berends-Giele recursion for pure-gluon amplitudes (oracle pin).
+"""Colour-ordered Berends-Giele recursion: all-gluon amplitudes and one quark line (oracle pin).
 
 An independent route to the all-gluon colour-basis amplitudes: Berends and
 Giele, Nucl. Phys. B306 (1988) 759, with the colour-ordered Feynman rules
@@ -87,6 +87,102 @@ def bg_amplitudes(spec: str, momenta: np.ndarray, hels=None):
         v, _ = current(w, prop=False)
         out[w] = L.mdot(v, waves[proc.root])
     return out
+
+
+def _gluon_current_fn(waves, moms):
+    """Memoised colour-ordered gluon current J(word) (with its propagator) and its momentum."""
+    cache = {}
+
+    def current(word, prop=True):
+        key = (word, prop)
+        if key in cache:
+            return cache[key]
+        if len(word) == 1:
+            res = (waves[word[0]], moms[word[0]])
+        else:
+            k = sum(moms[i] for i in word)
+            acc = 0
+            for s in range(1, len(word)):
+                (ja, ka), (jb, kb) = current(word[:s]), current(word[s:])
+                acc = acc + _v3(ja, ka, jb, kb)
+            for s in range(1, len(word) - 1):
+                for t in range(s + 1, len(word)):
+                    ja, _ = current(word[:s])
+                    jb, _ = current(word[s:t])
+                    jc, _ = current(word[t:])
+                    acc = acc + _v4(ja, jb, jc)
+            if prop:
+                acc = -1j * acc / L.mdot(k, k)[..., None]
+            res = (acc, k)
+        cache[key] = res
+        return res
+    return current
+
+
+def bg_quark_amplitudes(spec: str, momenta: np.ndarray, hels=None):
+    """Colour-ordered amplitudes of one quark line with gluons, by the Berends-Giele recursion.
+
+    The colour factor of ordering w = (w_1 ... w_k) of the gluons is the chain
+    (T^{w_1} ... T^{w_k})_{i j}, with i the colour of the row-spinor end of the line (outgoing
+    quark or incoming antiquark) and j that of the column-spinor end (incoming quark or outgoing
+    antiquark).  Reading the chain from the column end, the quark current that has absorbed the
+    gluon word (w_s+1 ... w_k) is
+
+        Q(w_s+1 ... w_k) = [i P/ / P^2] sum_{r} (i/sqrt2) G(w_s+1 ... w_r)/ Q(w_r+1 ... w_k)
+
+    with Q() the external column spinor, P the momentum along the fermion arrow (column end plus
+    the absorbed gluons, all momenta flowing in) and v/ = v_mu gamma^mu; the amplitude closes the
+    last vertex on the row spinor without a propagator:
+
+        A(w) = rowbar . sum_s (i/sqrt2) G(w_1 ... w_s)/ Q(w_s+1 ... w_k).
+
+    G(u) is the colour-ordered gluon current of the trace recursion for the sub-word u read
+    backwards, J(u_last ... u_first): a colour-ordered vertex lists its legs in one cyclic sense,
+    which along the quark line runs against the order of the chain.
+
+    Returns (words, dict word -> [H, N])."""
+    proc = parse_process(spec)
+    kinds = proc.kinds
+    qi = [i for i, k in enumerate(kinds) if k == "qi"]
+    qo = [i for i, k in enumerate(kinds) if k == "qo"]
+    if len(qi) != 1 or len(qo) != 1:
+        raise ValueError("this recursion covers processes with exactly one quark line")
+    gluons = tuple(i for i, k in enumerate(kinds) if k == "g")
+    p = np.asarray(momenta, dtype=np.float64)
+    if hels is None:
+        hels = helicity_table(proc.n)
+    waves, moms = _externals(proc, p, hels, None)
+    current = _gluon_current_fn(waves, moms)
+    col, row = waves[qi[0]], waves[qo[0]]
+    kcol = moms[qi[0]]
+    vertex = lambda j, psi: (1j / _S2) * np.einsum("...ab,...b->...a", L.slash(j), psi)
+    sub = lambda u: current(tuple(reversed(u)))[0]
+    qcache = {}
+
+    def quark(word):
+        """Column-spinor current after absorbing the gluon word (the rightmost part of the chain)."""
+        if word in qcache:
+            return qcache[word]
+        if not word:
+            res = col
+        else:
+            acc = 0
+            for r in range(1, len(word) + 1):
+                acc = acc + vertex(sub(word[:r]), quark(word[r:]))
+            q = kcol + sum(moms[i] for i in word)
+            res = 1j * np.einsum("...ab,...b->...a", L.slash(q), acc) / L.mdot(q, q)[..., None]
+        qcache[word] = res
+        return res
+
+    import itertools
+    out = {}
+    words = list(itertools.permutations(gluons))
+    for w in words:
+        acc = 0
+        for s in range(1, len(w) + 1):
+            acc = acc + vertex(sub(w[:s]), quark(w[s:]))
+        out[w] = np.einsum("...a,...a->...", row, acc)
+    return words, out
 
 
 def trace_word_to_bg(word: tuple, root: int) -> tuple:

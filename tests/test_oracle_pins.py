@@ -12,7 +12,7 @@ import pytest
 
 from oracle import oracle_me2, oracle_amplitudes
 from oracle import lorentz as L
-from oracle.berends_giele import bg_amplitudes, trace_word_to_bg
+from oracle.berends_giele import bg_amplitudes, bg_quark_amplitudes, trace_word_to_bg
 from oracle.colour import (all_assignments, basis_tensor_all, colour_basis, colour_data,
                            diagram_colour_values)
 from oracle.me2 import _evaluate, _externals, helicity_table
@@ -318,6 +318,68 @@ def test_berends_giele_matches_jamps(spec, n_ev):
     assert np.max(np.abs(r / r[0] - 1)) < 1e-10
     # magnitude fixed by the normalisations: J = 2^{n/2} g^{n-2} A
     assert abs(abs(r[0]) / (2 ** (n / 2) * g ** (n - 2)) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("spec,n_ev", [("u u~ > g g", 4), ("u u~ > g g g", 3), ("u u~ > g g g g", 2),
+                                       ("u g > u g g", 3), ("g u~ > g g u~", 2)])
+def test_berends_giele_quark_line_matches_jamps(spec, n_ev):
+    """Chain-basis amplitudes of one quark line equal the colour-ordered Berends-Giele quark-line
+    recursion times one real positive constant, 2^{k/2} g^{n-2} for k gluons (t = T / sqrt2 per
+    generator of the chain, one g per vertex)."""
+    p = _events(spec, n_ev, seed=16)
+    proc = parse_process(spec)
+    jamp, hels = oracle_amplitudes(spec, p, ALPHA_S)
+    _, bg = bg_quark_amplitudes(spec, p, hels)
+    basis = colour_basis(proc)
+    scale = 0.0
+    ratios = []
+    for a, desc in enumerate(basis):
+        a_bg = bg[tuple(desc[0][2])]
+        scale = max(scale, np.abs(a_bg).max())
+    for a, desc in enumerate(basis):
+        a_bg = bg[tuple(desc[0][2])]
+        big = np.abs(a_bg) > 1e-9 * scale
+        # where the recursion vanishes (helicity zeros) the diagram sum vanishes too
+        assert np.all(np.abs(jamp[..., a][~big]) < 1e-9 * np.abs(jamp).max())
+        ratios.append(jamp[..., a][big] / a_bg[big])
+    r = np.concatenate(ratios)
+    k = sum(1 for x in proc.kinds if x == "g")
+    expected = 2 ** (k / 2) * math.sqrt(G2) ** (proc.n - 2)
+    assert np.max(np.abs(r / expected - 1)) < 1e-10
+
+
+def test_parke_taylor_quark_line():
+    """One quark line, MHV: in the all-outgoing convention, with f- / f+ the quark-line ends of
+    negative / positive helicity and i the one negative-helicity gluon, every colour-ordered
+    |A(sigma)|^2 is |s_{f- i}|^3 |s_{f+ i}| / prod_cyclic |s_{adjacent}| times one constant (the
+    cyclic order runs from the row end of the chain over the gluons to its column end)."""
+    spec = "u u~ > g g g g"
+    p = _events(spec, 3, seed=19)
+    proc = parse_process(spec)
+    k = p.copy()
+    k[:, :2] *= -1                                   # all momenta outgoing
+    sij = lambda i, j: np.abs(_minkowski(k[:, i] + k[:, j]))
+    jamp, hels = oracle_amplitudes(spec, p, ALPHA_S)
+    out_hel = hels.copy()
+    out_hel[:, :2] *= -1                             # incoming helicity h is outgoing -h
+    basis = colour_basis(proc)
+    row, col = basis[0][0][0], basis[0][0][1]
+    gl = [i for i, x in enumerate(proc.kinds) if x == "g"]
+    ratios, seen = [], 0
+    for h in range(hels.shape[0]):
+        neg_g = [i for i in gl if out_hel[h, i] < 0]
+        if len(neg_g) != 1 or out_hel[h, row] == out_hel[h, col]:
+            continue
+        i = neg_g[0]
+        fm, fp = (row, col) if out_hel[h, row] < 0 else (col, row)
+        seen += 1
+        for a, desc in enumerate(basis):
+            order = [row] + list(desc[0][2]) + [col]
+            ps = np.prod([sij(order[x], order[(x + 1) % len(order)]) for x in range(len(order))], axis=0)
+            ratios.append(np.abs(jamp[h, :, a]) ** 2 * ps / (sij(fm, i) ** 3 * sij(fp, i)))
+    ratios = np.array(ratios)
+    assert seen == 8                                   # 2 quark-helicity assignments x 4 gluons
+    assert np.max(np.abs(ratios / ratios[0] - 1)) < 1e-10
 
 
 # ------------------------------------------------------------ exhaustive colour
