@@ -193,48 +193,187 @@ def fused_run(steps, precision="mixed", seed=7):
 
 
 SERVING_SPECS = ["g g > g g g", "g g > g g g g", "u u~ > g g g g g", "u u > u u g g g"]
+SERVING_POOL = 1 << 18
+SERVING_BATCH_LOG2 = (8, 18)
 
 
 def serving_run(n_requests, rate_hz=2000.0, seed=11):
-    """Poisson arrivals of mixed-process integrator batches through the serving loop."""
-    import torch
-    from paper_0909_5257_amd.heget import Process
+    """Poisson arrivals of mixed-process integrator batches through the serving loop (C5).
+
+    Three runs of the same server flow: the mixed path at the configuration's 2,000 requests/s, which
+    offers far more events per second than one GPU serves (the queue grows for the whole run, so the
+    latencies there are queueing delays); the mixed path at a stable rate (70 % of the events/s it
+    served in the first run); and the plain float64 path through the same server at 2,000 requests/s
+    and at its own stable rate.  Served results of every run are compared with the stored oracle
+    values of the events they contain."""
     from paper_0909_5257_amd.serving import Server, latency_summary, run_poisson
     from phasespace import KIN_C5, generate_events
-    pool = {}
+    pool, refs = {}, {}
+    names = {"g g > g g g": "gg_ggg_c5_2e18", "g g > g g g g": "gg_gggg_c5_2e18",
+             "u u~ > g g g g g": "uux_ggggg_c5_2e18", "u u > u u g g g": "uu_uuggg_c5_2e18"}
     for i, spec in enumerate(SERVING_SPECS):
         nf = len(spec.split(">")[1].split())
-        pool[spec] = generate_events(1 << 18, nf, KIN_C5, seed=seed, stream=i)
+        pool[spec] = generate_events(SERVING_POOL, nf, KIN_C5, seed=seed, stream=i)
+        refs[spec] = stored_oracle_sample(names[spec])
     log("[bench] serving pool ready")
+    lo2, hi2 = SERVING_BATCH_LOG2
+    mean_batch = (2 ** hi2 - 2 ** lo2) / ((hi2 - lo2) * math.log(2))
 
     def workload(rng):
         spec = SERVING_SPECS[rng.integers(len(SERVING_SPECS))]
-        n = int(2 ** rng.uniform(8, 18))
-        lo = int(rng.integers(0, (1 << 18) - n + 1))
-        return spec, pool[spec][lo:lo + n]
+        n = int(2 ** rng.uniform(lo2, hi2))
+        lo = int(rng.integers(0, SERVING_POOL - n + 1))
+        return spec, (lo, pool[spec][lo:lo + n])
 
-    server = Server(SERVING_SPECS, precisions=("mixed",), hbm_budget_bytes=16 << 30, n_streams=4)
-    # warm the kernels once
-    for spec in SERVING_SPECS:
-        server.submit(spec, pool[spec][:256])
-    server.drain()
-    server.completed.clear()
-    reqs, wall = run_poisson(server, workload, rate_hz, n_requests, seed=seed)
-    served = latency_summary(reqs)
-    log(f"[bench] served {served}")
-    # the plain float64 path on the same requests, one at a time
-    procs = {s: Process(s, "fp64") for s in SERVING_SPECS}
-    t0 = time.perf_counter()
-    n_ev = 0
-    for r in reqs:
-        x = torch.from_numpy(r.momenta).to("cuda")
-        procs[r.spec].matrix_elements(x, ALPHA_S)
+    def run(precision, rate, count):
+        server = Server(SERVING_SPECS, precisions=(precision,), hbm_budget_bytes=16 << 30, n_streams=4)
+        for spec in SERVING_SPECS:          # warm the kernels once
+            server.submit(spec, pool[spec][:256], precision)
+        server.drain()
+        server.completed.clear()
+        offsets = []                         # pool offset of each request, in submission order
+
+        def wl(rng):
+            spec, (lo, mom) = workload(rng)
+            offsets.append(lo)
+            return spec, mom
+        reqs, wall = run_poisson(server, wl, rate, count, seed=seed, precision=precision)
+        summary = latency_summary(reqs)
+        offered = rate * mean_batch
+        # oracle check of every served event that is in the stored sample
+        got, want = [], []
+        for r, lo in zip(reqs, offsets):
+            idx, val = refs[r.spec]
+            sel = (idx >= lo) & (idx < lo + r.n)
+            got.append(r.result[idx[sel] - lo])
+            want.append(val[sel])
+        err = rel_err(np.concatenate(got), np.concatenate(want)) if got else None
+        queue = max(r.t_start - r.t_submit for r in reqs)
+        summary.update({"precision": precision, "rate_hz": rate, "offered_events_per_s": offered,
+                        "served_events_per_s": summary.pop("events_per_s"), "max_queue_wait_ms": queue * 1e3,
+                        "rel_err_vs_oracle": err,
+                        "overloaded": offered > summary["events"] / max(wall, 1e-9) * 1.05})
+        log(f"[bench] serving {precision} at {rate:.0f} req/s: {summary}")
+        return summary
+
+    over = run("mixed", rate_hz, n_requests)
+    stable_rate = 0.7 * over["served_events_per_s"] / mean_batch
+    stable = run("mixed", stable_rate, max(200, n_requests // 2))
+    plain_over = run("fp64", rate_hz, n_requests)
+    plain_rate = 0.7 * plain_over["served_events_per_s"] / mean_batch
+    plain_stable = run("fp64", plain_rate, max(200, n_requests // 2))
+    return {"processes": SERVING_SPECS, "batch": f"log-uniform [{2 ** lo2}, {2 ** hi2}]",
+            "mean_batch_events": mean_batch, "kinematics": "sqrt(s) U[300,3000] GeV, pT>20, |eta|<2.5, dR>0.4",
+            "mixed_at_config_rate": over, "mixed_at_stable_rate": stable,
+            "fp64_at_config_rate": plain_over, "fp64_at_stable_rate": plain_stable,
+            "mixed_over_fp64_served": over["served_events_per_s"] / plain_over["served_events_per_s"]}
+
+
+def stored_oracle_sample(name):
+    """(indices, |M|^2) of a stored oracle sample (tests/golden/oracle_<name>.txt: values the FP64
+    oracle computed for seeded events of the same workload, written by make_oracle_samples.py)."""
+    idx, val = [], []
+    with open(os.path.join(ROOT, "tests", "golden", f"oracle_{name}.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                i, v = line.split()
+                idx.append(int(i))
+                val.append(float(v))
+    return np.array(idx, dtype=np.int64), np.array(val)
+
+
+def rel_err(got, ref):
+    rel = np.abs(np.asarray(got) / np.asarray(ref) - 1.0)
+    return {"max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel)),
+            "n": int(rel.size)}
+
+
+# The single-process configurations: (label, process, events, kinematics, seed, stream, stored oracle sample)
+CONFIG_ROWS = [
+    ("C1", "g g > g g", 65536, "C1", 0, 0, "gg_gg_c1_65536"),
+    ("C2", "u u~ > g g g g", 1 << 20, "C2", 0, 0, "uux_gggg_c2_2e20"),
+    ("C2", "u u > u u g g", 1 << 20, "C2", 0, 1, "uu_uugg_c2_2e20"),
+]
+
+
+def config_rows_run(torch, steps, warmup):
+    """Events/s, roofline fraction and error vs the stored oracle samples of C1 and C2, both precisions."""
+    from phasespace import KIN_C1, KIN_C2, generate_events
+    from paper_0909_5257_amd.heget import Process
+    kins = {"C1": KIN_C1, "C2": KIN_C2}
+    out = []
+    for label, spec, n, kin, seed, stream, sample in CONFIG_ROWS:
+        nf = len(spec.split(">")[1].split())
+        x = torch.from_numpy(generate_events(n, nf, kins[kin], seed=seed, stream=stream)).to("cuda")
+        res = torch.empty(n, dtype=torch.float64, device="cuda")
+        idx, ref = stored_oracle_sample(sample)
+        row = {"config": label, "process": spec, "events": n}
+        for precision in ("fp64", "mixed"):
+            pr = Process(spec, precision)
+            ms = _timed(torch, lambda: pr.matrix_elements(x, ALPHA_S, out=res), steps, warmup)
+            flops = pr.flops_per_event()
+            tf = flops * n / (ms * 1e-3) / 1e12
+            row[precision] = {"ms_per_launch": ms, "events_per_s": n / (ms * 1e-3), "algorithmic_tflops": tf,
+                              "frac_of_alu_peak": tf / PEAK_ALU_TFLOPS,
+                              "rel_err_vs_oracle": rel_err(res.cpu().numpy()[idx], ref)}
+        log(f"[bench] {label} {spec}: fp64 {row['fp64']['events_per_s']:.3e}, mixed "
+            f"{row['mixed']['events_per_s']:.3e} events/s; max rel err {row['fp64']['rel_err_vs_oracle']['max']:.1e} "
+            f"/ {row['mixed']['rel_err_vs_oracle']['max']:.1e}")
+        out.append(row)
+        del x, res
+    return out
+
+
+def end_to_end_run(torch, workload, inputs, steps):
+    """The paper's timer scope (section 5.2): from the start of the host-to-device transfer to the end of
+    the device-to-host transfer of the results, for the benchmark batches in the mixed path, from
+    pinned host memory; and the same with the momenta made on the device (RAMBO from host uniforms)."""
+    from phasespace import KIN_C2, rambo_uniforms
+    from paper_0909_5257_amd import heget
+    procs = [heget.Process(spec, "mixed") for spec, _, _ in workload]
+    host_in = [torch.from_numpy(p).pin_memory() for p in inputs]
+    host_out = [torch.empty(n, dtype=torch.float64).pin_memory() for _, n, _ in workload]
+    dev_in = [torch.empty_like(h, device="cuda") for h in host_in]
+    dev_out = [torch.empty(n, dtype=torch.float64, device="cuda") for _, n, _ in workload]
+
+    def momenta_path():
+        for pr, hi, di, do, ho in zip(procs, host_in, dev_in, dev_out, host_out):
+            di.copy_(hi, non_blocking=True)
+            pr.matrix_elements(di, ALPHA_S, out=do)
+            ho.copy_(do, non_blocking=True)
         torch.cuda.synchronize()
-        n_ev += r.n
-    plain = n_ev / (time.perf_counter() - t0)
-    served.update({"rate_hz": rate_hz, "processes": SERVING_SPECS, "batch": "log-uniform [256, 262144]",
-                   "precision": "mixed", "plain_fp64_serial_events_per_s": plain})
-    return served
+
+    # random numbers in, results out: sqrt(s) and 4 uniforms per final parton per event
+    uni = []
+    for (spec, n, stream), pr in zip(workload, procs):
+        rs, u = rambo_uniforms(n, pr.n_ext - 2, KIN_C2, seed=0, stream=stream)
+        uni.append((torch.from_numpy(rs).pin_memory(), torch.from_numpy(u).pin_memory()))
+    dev_uni = [(torch.empty_like(a, device="cuda"), torch.empty_like(b, device="cuda")) for a, b in uni]
+    bufs = [(torch.empty((n, pr.n_ext, 4), dtype=torch.float64, device="cuda"),
+             torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+             torch.empty(2, dtype=torch.float64, device="cuda")) for (_, n, _), pr in zip(workload, procs)]
+
+    def uniforms_path():
+        for pr, (hr, hu), (dr, du), b, ho in zip(procs, uni, dev_uni, bufs, host_out):
+            dr.copy_(hr, non_blocking=True)
+            du.copy_(hu, non_blocking=True)
+            heget.integrate_step(pr, dr, du, ALPHA_S, 20.0, 2.5, 0.4, out=b)
+            ho.copy_(b[1], non_blocking=True)
+        torch.cuda.synchronize()
+
+    total = sum(n for _, n, _ in workload)
+    res = {"precision": "mixed", "events": total,
+           "h2d_bytes_momenta": int(sum(h.numel() * 8 for h in host_in)),
+           "h2d_bytes_uniforms": int(sum((a.numel() + b.numel()) * 8 for a, b in uni))}
+    for name, fn in (("momenta_h2d_kernel_d2h", momenta_path), ("uniforms_h2d_rambo_kernel_cuts_d2h", uniforms_path)):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms_per_step": dt * 1e3, "events_per_s": total / dt}
+        log(f"[bench] end-to-end {name}: {total / dt:.3e} events/s")
+    return res
 
 
 def _timed(torch, fn, steps, warmup):
@@ -349,7 +488,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="small batches, for a smoke run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=48, help="0 disables the serving run")
+    ap.add_argument("--serving-requests", type=int, default=1000, help="0 disables the serving run")
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the helicity Monte Carlo, colour GEMM and integration measurements")
@@ -438,8 +577,20 @@ def main():
             for (spec, _, _), (idx, ref), out in zip(workload, refs, r["out"]):
                 errs[spec] = float(np.max(np.abs(out[idx] / ref - 1.0)))
             accuracy[precision] = errs
+    # the stored oracle values of 512 sampled events of each full-size batch
+    stored = {}
+    if not args.quick:
+        names = {"u u~ > g g g g g": "uux_ggggg_c2_2e20", "g g > g g g g": "gg_gggg_c2_2e21"}
+        for precision, r in results.items():
+            stored[precision] = {}
+            for (spec, _, _), out in zip(workload, r["out"]):
+                idx, ref = stored_oracle_sample(names[spec])
+                stored[precision][spec] = rel_err(out[idx], ref)
 
     extras = {}
+    if not args.no_extras and not args.quick:
+        extras["config_rows"] = config_rows_run(torch, args.steps, args.warmup)
+        extras["end_to_end"] = end_to_end_run(torch, workload, inputs, max(1, min(args.steps, 3)))
     if not args.no_extras:
         extras["helicity_mc"] = helicity_mc_run(torch, workload, dev_inputs, args.steps, args.warmup)
         extras["colour_gemm_c3"] = colour_gemm_run(torch, workload[1][1], args.steps, args.warmup)
@@ -472,6 +623,7 @@ def main():
                  "per_process": summary["fp64"]["per_process"], "roofline": summary["fp64"]["roofline"]},
         "mixed_over_fp64": head["events_per_s"] / summary["fp64"]["events_per_s"],
         "max_rel_err_vs_oracle": accuracy,
+        "rel_err_vs_stored_oracle_sample": stored,
         "serving": serving,
         "fused_batch": fused,
         **extras,

@@ -34,6 +34,11 @@ CANDIDATES = {
     # externals kept in registers, other budgets
     "keep160": {"double": {"budget": 160}, "float": {"budget": 160}},
     "keep200": {"double": {"budget": 192}, "float": {"budget": 200}},
+    "keep224": {"double": {"budget": 224}, "float": {"budget": 224}},
+    # one wave per 64-event group where the colour vector is small enough: no cross-wave
+    # accumulation, bit-reproducible results
+    "group176s": {"double": {"externals": "group", "budget": 176},
+                  "float": {"externals": "group", "budget": 176, "waves_per_cu": 4}},
 }
 DEFAULT_PROCESSES = ["g g > g g g g", "u u~ > g g g g", "u u~ > g g g g g", "u u > u u g g", "u u > u u g g g",
                      "u g > u g g g"]
@@ -115,9 +120,16 @@ def _measure(args):
         json.dump(results, f, indent=1)
 
 
+def _current_table() -> dict:
+    from .gen.tuned import TUNED
+    return dict(TUNED)
+
+
 def _apply(args):
     timings = json.load(open(os.path.join(args.out, "timings.json")))
-    chosen = {}
+    # settings of processes this run did not time stay as they are
+    timed = {k.split("|")[0] for k in timings["default"]}
+    chosen = {key: val for key, val in _current_table().items() if key[0] not in timed}
     keys = sorted(timings["default"])
     for key in keys:
         spec, prec = key.split("|")

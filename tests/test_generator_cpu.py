@@ -199,7 +199,11 @@ def test_tuner_keeps_only_clear_wins(tmp_path):
     (tmp_path / "timings.json").write_text(json.dumps(timings))
     table = tmp_path / "tuned.py"
     chosen = tune.main(["apply", "--out", str(tmp_path), "--table", str(table)])
-    assert set(chosen) == {("g g > g g g", "double")}          # 1 % on mixed is within the margin
+    # 1 % on mixed is within the margin
+    assert {key for key in chosen if key[0] == "g g > g g g"} == {("g g > g g g", "double")}
+    from paper_0909_5257_amd.gen.tuned import TUNED
+    # settings of processes that were not timed are kept as they are
+    assert all(chosen[key] == val for key, val in TUNED.items() if key[0] != "g g > g g g")
     assert chosen[("g g > g g g", "double")]["budget"] == tune.CANDIDATES["group208"]["double"]["budget"]
     loaded = runpy.run_path(str(table))["TUNED"]
     assert loaded[("g g > g g g", "double")]["externals"] == "group"
