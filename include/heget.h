@@ -245,6 +245,23 @@ heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const dou
                                   const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
                                   double* me2, double* weight, double* sums, void* stream);
 
+/* heget_integrate_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, but the block partial sums go to a fixed 2 MiB device
+ * array that the library holds on every GPU it runs on until the process ends,
+ * and nothing is allocated or freed.  With helicity != NULL the events are not
+ * sorted by chirality pattern first (same results; two-quark-line processes run
+ * slower).  Arguments and results as heget_integrate_step.
+ *   n_events  1 .. 2^25 (33,554,432); larger batches return HEGET_E_INVALID_ARG.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different streams or host threads without ordering between them) race and
+ * give wrong sums.  Calls ordered on one stream are safe.
+ * Errors: HEGET_E_INVALID_ARG, HEGET_E_DEVICE. */
+heget_status heget_integrate_step_noalloc(heget_process_t p, int64_t n_events, const double* sqrt_s,
+                                          const double* uniforms, const int32_t* helicity, double alpha_s,
+                                          const heget_cuts* cuts, double* momenta, double* me2, double* weight,
+                                          double* sums, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Test hooks (not on the hot path).  They let a test compare the amplitudes
  * themselves, not only |M|^2, with an independent implementation.

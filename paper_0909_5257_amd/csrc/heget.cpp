@@ -139,6 +139,14 @@ heget_status heget_matrix_elements(heget_process_t p, const double* momenta, int
 
 heget_status heget_matrix_elements_helicity(heget_process_t p, const double* momenta, const int32_t* helicity,
                                             int64_t n_events, double alpha_s, double* me2, void* stream) {
+  return heget_detail_matrix_elements_helicity(p, momenta, helicity, n_events, alpha_s, me2, stream, true);
+}
+
+}  // extern "C"
+
+heget_status heget_detail_matrix_elements_helicity(heget_process_t p, const double* momenta, const int32_t* helicity,
+                                                   int64_t n_events, double alpha_s, double* me2, void* stream,
+                                                   bool allow_sort) {
   if (!p) return HEGET_E_INVALID_ARG;
   if (n_events < 0 || n_events > (int64_t(1) << 36)) return HEGET_E_INVALID_ARG;
   if (!(alpha_s > 0.0) || !std::isfinite(alpha_s)) return HEGET_E_INVALID_ARG;
@@ -152,7 +160,8 @@ heget_status heget_matrix_elements_helicity(heget_process_t p, const double* mom
   // one term of the helicity sum: 1/4 initial spin average and the couplings, no flip factor
   const double scale = 0.25 * std::pow(g2, p->desc->n_ext - 2);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (p->pattern_dev == nullptr || n_events >= (int64_t(1) << 31) || n_events > p->desc->max_launch_events) {
+  if (!allow_sort || p->pattern_dev == nullptr || n_events >= (int64_t(1) << 31) ||
+      n_events > p->desc->max_launch_events) {
     hipError_t e = p->desc->launch(p->precision, momenta, helicity, nullptr, n_events, me2, p->colour_table_dev,
                                    scale, s);
     return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
@@ -187,6 +196,8 @@ heget_status heget_matrix_elements_helicity(heget_process_t p, const double* mom
     if (b) (void)hipFreeAsync(b, s);
   return st;
 }
+
+extern "C" {
 
 heget_status heget_matrix_elements_hook(heget_process_t p, const double* momenta, int64_t n_events, double alpha_s,
                                         int gauge_leg, double* me2, double* jamp, void* stream) {

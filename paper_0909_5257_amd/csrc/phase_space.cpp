@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "heget.h"
 #include "heget_internal.hpp"
@@ -159,6 +161,38 @@ __global__ __launch_bounds__(kThreads) void sum_kernel(int64_t nblocks, const do
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// Work space of heget_integrate_step_noalloc: the weight kernel's per-block partial sums (f, f^2),
+// one pair per 256 events, in a fixed device array instead of stream-ordered allocations.  Every
+// block of a launch writes its own pair, so nothing has to be cleared between calls.
+constexpr int64_t kScratchBlocks = int64_t(1) << 17;                  // 2 MiB: up to 2^25 events
+constexpr int64_t kNoallocMaxEvents = kScratchBlocks * kThreads;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[2 * kScratchBlocks];
+
+namespace {
+
+// Device address of `scratch` on each device (host code may not use the symbol's name itself).
+std::mutex g_scratch_mutex;
+std::map<int, double*> g_scratch_ptr;
+
+hipError_t scratch_for_current_device(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    it = g_scratch_ptr.emplace(dev, static_cast<double*>(ptr)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
 bool valid_cuts(const heget_cuts* c) {
   return c && std::isfinite(c->pt_min) && std::isfinite(c->eta_max) && std::isfinite(c->delta_r_min) &&
          c->eta_max > 0.0;
@@ -205,9 +239,16 @@ heget_status heget_apply_cuts(int n_ext, int64_t n_events, const double* momenta
   return hipGetLastError() == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
 }
 
-heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const double* sqrt_s, const double* uniforms,
-                                  const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
-                                  double* me2, double* weight, double* sums, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Both integration-step entry points: with part == nullptr the block partials are taken from and
+// returned to the stream-ordered pool, otherwise they go to part (at least 2 * blocks(n) doubles)
+// and nothing is allocated (the sampled-helicity mode then runs without the chirality sort).
+heget_status integrate_step(heget_process_t p, int64_t n_events, const double* sqrt_s, const double* uniforms,
+                            const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
+                            double* me2, double* weight, double* sums, void* stream, double* part) {
   int n_ext = 0;
   if (!p || heget_process_info(p, &n_ext, nullptr, nullptr, nullptr) != HEGET_OK) return HEGET_E_INVALID_ARG;
   if (n_events <= 0 || n_events > (int64_t(1) << 36) || !valid_cuts(cuts)) return HEGET_E_INVALID_ARG;
@@ -216,21 +257,44 @@ heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const dou
   if (!(alpha_s > 0.0) || !std::isfinite(alpha_s)) return HEGET_E_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (launch_rambo(n_ext - 2, n_events, sqrt_s, uniforms, momenta, nullptr, s) != hipSuccess) return HEGET_E_DEVICE;
-  heget_status st = helicity ? heget_matrix_elements_helicity(p, momenta, helicity, n_events, alpha_s, me2, stream)
+  const bool own = part == nullptr;
+  heget_status st = helicity ? heget_detail_matrix_elements_helicity(p, momenta, helicity, n_events, alpha_s, me2,
+                                                                     stream, own)
                              : heget_matrix_elements(p, momenta, n_events, alpha_s, me2, stream);
   if (st != HEGET_OK) return st;
   // identical final partons: 1 / prod(k!) over the species of the final state
   double factor = kGeV2pb / heget_detail_final_symmetry(p);
   if (helicity) factor *= (double)(int64_t(1) << n_ext);   // one sampled configuration stands for 2^n
   const int64_t nb = blocks(n_events);
-  double* part = nullptr;
-  if (hipMallocAsync(&part, sizeof(double) * 2 * nb, s) != hipSuccess) return HEGET_E_OUT_OF_MEMORY;
+  if (own && hipMallocAsync(&part, sizeof(double) * 2 * nb, s) != hipSuccess) return HEGET_E_OUT_OF_MEMORY;
   hipLaunchKernelGGL(weight_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, n_ext, n_events, momenta, me2, factor,
                      cuts->pt_min, cuts->eta_max, cuts->delta_r_min, weight, part);
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s, nb, part, sums);
   const hipError_t e = hipGetLastError();
-  (void)hipFreeAsync(part, s);
+  if (own) (void)hipFreeAsync(part, s);
   return e == hipSuccess ? HEGET_OK : HEGET_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const double* sqrt_s, const double* uniforms,
+                                  const int32_t* helicity, double alpha_s, const heget_cuts* cuts, double* momenta,
+                                  double* me2, double* weight, double* sums, void* stream) {
+  return integrate_step(p, n_events, sqrt_s, uniforms, helicity, alpha_s, cuts, momenta, me2, weight, sums, stream,
+                        nullptr);
+}
+
+heget_status heget_integrate_step_noalloc(heget_process_t p, int64_t n_events, const double* sqrt_s,
+                                          const double* uniforms, const int32_t* helicity, double alpha_s,
+                                          const heget_cuts* cuts, double* momenta, double* me2, double* weight,
+                                          double* sums, void* stream) {
+  if (n_events > kNoallocMaxEvents) return HEGET_E_INVALID_ARG;
+  double* part = nullptr;
+  if (n_events > 0 && scratch_for_current_device(&part) != hipSuccess) return HEGET_E_DEVICE;
+  return integrate_step(p, n_events, sqrt_s, uniforms, helicity, alpha_s, cuts, momenta, me2, weight, sums, stream,
+                        part);
 }
 
 }  // extern "C"

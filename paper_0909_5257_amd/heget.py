@@ -75,6 +75,8 @@ def lib():
     L.heget_apply_cuts.restype = i32
     L.heget_integrate_step.argtypes = [vp, i64, vp, vp, vp, dbl, ctypes.POINTER(Cuts), vp, vp, vp, vp, vp]
     L.heget_integrate_step.restype = i32
+    L.heget_integrate_step_noalloc.argtypes = [vp, i64, vp, vp, vp, dbl, ctypes.POINTER(Cuts), vp, vp, vp, vp, vp]
+    L.heget_integrate_step_noalloc.restype = i32
     L.heget_colour_reduction.argtypes = [vp, pi32, pi32, pi64, pi64, pi64, pi64, pi32]
     L.heget_colour_reduction.restype = i32
     L.heget_matrix_elements_hook.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
@@ -341,8 +343,11 @@ def apply_cuts(momenta, pt_min: float, eta_max: float, delta_r_min: float, strea
 
 
 def integrate_step(proc: Process, sqrt_s, uniforms, alpha_s: float, pt_min: float, eta_max: float,
-                   delta_r_min: float, helicity=None, stream=None):
-    """One device integration step; returns (momenta, me2, weight, sums[2]) GPU tensors."""
+                   delta_r_min: float, helicity=None, stream=None, out=None, noalloc: bool = False):
+    """One device integration step; returns (momenta, me2, weight, sums[2]) GPU tensors.
+
+    out: optional tuple of preallocated (momenta, me2, weight, sums) tensors to write.
+    noalloc: call heget_integrate_step_noalloc (no device allocation inside the library)."""
     import torch
     n = uniforms.shape[0]
     _dev_f64(sqrt_s, (n,), "sqrt_s")
@@ -350,13 +355,22 @@ def integrate_step(proc: Process, sqrt_s, uniforms, alpha_s: float, pt_min: floa
     if helicity is not None and (helicity.dtype != torch.int32 or not helicity.is_cuda or helicity.shape != (n,)):
         raise TypeError("helicity must be an int32 GPU tensor [N]")
     dev = uniforms.device
-    mom = torch.empty((n, proc.n_ext, 4), dtype=torch.float64, device=dev)
-    me2 = torch.empty(n, dtype=torch.float64, device=dev)
-    w = torch.empty(n, dtype=torch.float64, device=dev)
-    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    if out is None:
+        mom = torch.empty((n, proc.n_ext, 4), dtype=torch.float64, device=dev)
+        me2 = torch.empty(n, dtype=torch.float64, device=dev)
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        sums = torch.empty(2, dtype=torch.float64, device=dev)
+    else:
+        mom, me2, w, sums = out
+        _dev_f64(mom, (n, proc.n_ext, 4), "momenta")
+        _dev_f64(me2, (n,), "me2")
+        _dev_f64(w, (n,), "weight")
+        _dev_f64(sums, (2,), "sums")
     cuts = Cuts(pt_min, eta_max, delta_r_min)
-    _check(lib().heget_integrate_step(proc.handle, n, sqrt_s.data_ptr(), uniforms.data_ptr(),
-                                      None if helicity is None else helicity.data_ptr(), alpha_s,
-                                      ctypes.byref(cuts), mom.data_ptr(), me2.data_ptr(), w.data_ptr(),
-                                      sums.data_ptr(), _stream_ptr(stream)), "heget_integrate_step")
+    fn = lib().heget_integrate_step_noalloc if noalloc else lib().heget_integrate_step
+    _check(fn(proc.handle, n, sqrt_s.data_ptr(), uniforms.data_ptr(),
+              None if helicity is None else helicity.data_ptr(), alpha_s,
+              ctypes.byref(cuts), mom.data_ptr(), me2.data_ptr(), w.data_ptr(),
+              sums.data_ptr(), _stream_ptr(stream)),
+           "heget_integrate_step_noalloc" if noalloc else "heget_integrate_step")
     return mom, me2, w, sums
