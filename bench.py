@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("0ac045b9af34f640", 406954),
-    ("g g > g g g g", "fp64"): ("789094078d751f3b", 132738),
-    ("u u~ > g g g g g", "mixed"): ("62f7ed8697a255af", 429531),
-    ("g g > g g g g", "mixed"): ("0861d2f519c7e7d3", 65920),
+    ("u u~ > g g g g g", "fp64"): ("fb662da97a82d942", 409368),
+    ("g g > g g g g", "fp64"): ("eed2264c1b4a5d30", 52980),
+    ("u u~ > g g g g g", "mixed"): ("985390c88536bfa7", 419847),
+    ("g g > g g g g", "mixed"): ("18bf562c3869fcf4", 161415),
 }
 
 

@@ -238,7 +238,13 @@ heget_status heget_apply_cuts(int n_ext, int64_t n_events, const double* momenta
  *                is NOT applied here; it is the entry point's output).
  *   weight       DEVICE float64 [n_events], written: f_e.
  *   sums         DEVICE float64 [2], written: sum f_e and sum f_e^2, added in a
- *                fixed order (identical on every run).
+ *                fixed order, so they are identical on every run whenever me2 is.
+ *                me2 is bit-reproducible for kernels that give each group of 64
+ *                events one wave; kernels that share a group between several waves
+ *                (large colour spaces, e.g. u u~ > g g g g g) add the waves'
+ *                float64 colour-vector contributions in whatever order they
+ *                arrive, so me2 and the sums can differ between runs by float64
+ *                rounding (about 1e-16 relative).
  * Work space for block partials is taken and returned in stream order.
  * Errors: HEGET_E_INVALID_ARG, HEGET_E_OUT_OF_MEMORY, HEGET_E_DEVICE. */
 heget_status heget_integrate_step(heget_process_t p, int64_t n_events, const double* sqrt_s, const double* uniforms,

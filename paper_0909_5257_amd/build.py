@@ -52,7 +52,7 @@ FLAGS = [
 # tuning knobs of the kernel planner, overridable from the environment (HEGET_<NAME>); the
 # per-precision ones take "float64_value,float32_value"
 for _name in ("CHUNK_FLOPS", "COOP_CHUNK_FLOPS", "TARGET_WAVES_PER_CU", "FORCE_WAVES",
-              "MERGE_WAVE_CHUNKS", "MERGE_MAX_PATTERN_CHUNKS"):
+              "MERGE_WAVE_CHUNKS", "MERGE_MAX_PATTERN_FLOPS"):
     if os.environ.get("HEGET_" + _name):
         from .gen import emit as _emit
         _val = os.environ["HEGET_" + _name]

@@ -120,7 +120,8 @@ __device__ __forceinline__ double wsym(const double* __restrict__ n, int k, int 
   return ba < bb ? 2.0 * v : v;
 }
 
-// Wave tile: 16 real rows.  Lane l works on row t = l % 16 and lane group g = l / 16.
+// Wave tile: 16 real rows.  Lane l works on row t = l % 16 and lane group g = l / 16.  The A and B
+// operands of the 16x16x4 instructions put A[i][k] in lane i + 16 k and B[k][j] in lane j + 16 k.
 // x[A][s] = x_t[16 A + 4 g + s]: the MFMA B operand of inner step s of block A (inner index g of
 // the instruction is colour 16 A + 4 g + s) and, for output block B = A, the four values that
 // the lane's output elements D[i] = Y^T[16 B + 4 g + i][t] are dotted with.
@@ -163,7 +164,13 @@ __global__ __launch_bounds__(64 * kWaves) void qf_mfma4(int k, const double* __r
     int bb = 0;
     while ((bb + 1) * (bb + 2) / 2 <= p) ++bb;
     const int ba = p - bb * (bb + 1) / 2;
-    ws[e] = (T)wsym(nmat, k, 16 * ba + 4 * (l >> 4) + s, 16 * bb + (l & 15));
+    // output row i of the instruction is colour 16 B + m(i): the float32 instruction leaves row i in
+    // lane group i / 4, register i % 4, and the float64 one in lane group i % 4, register i / 4, so
+    // for float64 the rows are transposed (m(i) = 4 (i % 4) + i / 4) to put the same colours
+    // 16 B + 4 g + r in lane group g, register r in both cases
+    const int i = l & 15;
+    const int m = sizeof(T) == 8 ? 4 * (i & 3) + (i >> 2) : i;
+    ws[e] = (T)wsym(nmat, k, 16 * ba + 4 * (l >> 4) + s, 16 * bb + m);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -74,6 +74,19 @@ HD mom4<double> add(const mom4<double>& a, const mom4<double>& b) {
 }
 template <class R> HD mom4<R> to(const mom4<double>& p) { return {(R)p.e, (R)p.x, (R)p.y, (R)p.z}; }
 
+// 1/P^2 of a propagator from its float64 invariant.  float: the hardware reciprocal of the rounded
+// invariant (1 ulp of float).  double: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r), each of which squares the relative error, to about 1 ulp of double.
+template <class R> HD R inv_msq(const mom4<double>& p);
+template <> HD float inv_msq<float>(const mom4<double>& p) { return __builtin_amdgcn_rcpf((float)msq(p)); }
+template <> HD double inv_msq<double>(const mom4<double>& p) {
+  const double x = msq(p);
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 // ------------------------------------------------------------ external states
 
 // Polarisation of a massless gluon with physical momentum p and helicity lam.

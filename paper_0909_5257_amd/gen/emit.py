@@ -33,7 +33,7 @@ from .reduce import ColourSpace
 from .tuned import TUNED as _TUNED_TABLE
 
 FLOPS = {   # real floating-point operations per call, counted from the routines
-    "vvv": 166, "gggg": 134, "iov": 58,
+    "vvv": 166, "gggg": 134, "iov": 58, "vvvx": 166, "ggggx": 134, "iovx": 58,
     "jvv": 156, "jggg": 120, "jio": 64, "fvi": 74, "fvo": 74,
     "ext": 40, "psum": 4, "inv": 8, "class_add": 4, "jamp_add": 4,
 }
@@ -41,6 +41,9 @@ FLOPS = {   # real floating-point operations per call, counted from the routines
 CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one chunk function
 # the same when several waves share a workgroup: finer for float32 so that eight waves balance
 COOP_CHUNK_FLOPS = {"double": 40000, "float": 20000}
+# ... but at most 1 / COOP_CHUNKS_PER_WAVE of a wave's share of the pattern, so that the longest-
+# first assignment of chunks to waves can balance them
+COOP_CHUNKS_PER_WAVE = 16
 LDS_PER_CU = 160 * 1024   # bytes of LDS per compute unit (gfx950)
 # resident waves per CU the workgroup shape aims for.  float32 code fits 256 registers, so two
 # waves per SIMD hide each other's latency; float64 code needs more (the allocator keeps the
@@ -49,12 +52,16 @@ TARGET_WAVES_PER_CU = {"double": 4, "float": 8}
 FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process and precision (for tuning)
 # Each call of a chunk function saves and restores the callee-saved registers it uses (scratch
 # traffic), so a wave's consecutive chunks are merged into one called function of up to this many
-# chunks.  Merged functions compile more slowly; patterns with more than MERGE_MAX_PATTERN_CHUNKS
-# chunks (g g > g g g g g) keep one function per chunk so that no translation unit takes much
-# longer than a quarter of an hour (merged, its float64 unit took more than 40 minutes).
-MERGE_WAVE_CHUNKS = 8
-MERGE_MAX_PATTERN_CHUNKS = 48
+# chunks.  Merged functions compile more slowly; patterns with more than MERGE_MAX_PATTERN_FLOPS
+# arithmetic per configuration (g g > g g g g g) keep one function per chunk so that no translation
+# unit takes much longer than a quarter of an hour (merged, its float64 unit took more than 40
+# minutes).
+MERGE_WAVE_CHUNKS = 16
+MERGE_MAX_PATTERN_FLOPS = 1_500_000
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
+# How amplitudes are packed into register groups: "greedy" (whole colour classes, each group grown by
+# the class that shares the most currents with it) or "classes" (first-seen class order, cut anywhere).
+PLAN = "greedy"
 # Per (process, precision) settings that measured faster on MI355X than the defaults above
 # (gen/tuned.py, written by python -m paper_0909_5257_amd.tune): "externals": "group" rebuilds
 # each external wavefunction inside every group from the LDS momenta (nothing stays live across
@@ -104,6 +111,8 @@ def _active(dag: Dag, hq: dict):
         good = all(ok[a] for a in amp.args)
         if good and amp.op == "iov":
             good = hq[nd[amp.args[0]].end] == hq[root]
+        elif good and amp.op == "iovx":
+            good = hq[nd[amp.args[0]].end] == hq[nd[amp.args[1]].end]
         if good:
             amps.append(i)
     return amps
@@ -240,7 +249,7 @@ class _Group:
         key = ("I", mask)
         if key not in self.defs:
             p = self.psum(mask)
-            self.lines.append(f"  const R {self.name(key)} = R(1.0 / msq({p}));")
+            self.lines.append(f"  const R {self.name(key)} = inv_msq<R>({p});")
             self._def(key, SIZES[self.prec]["inv"])
             self.flops += FLOPS["inv"]
         self._use(key)
@@ -311,6 +320,9 @@ class _Group:
         root = em.proc.root
         nd = em.dag.nodes
         args = [self.node(a) for a in amp.args]
+        if amp.op in ("vvvx", "ggggx", "iovx"):
+            self._closed_amplitude(ai, amp, args, acc, fac)
+            return
         r = self.node(em.dag.ext[root])
         if amp.op == "vvv":
             x, y = amp.args
@@ -329,6 +341,29 @@ class _Group:
         for a in amp.args:
             self._use(("c", a))
         self._use(("c", em.dag.ext[root]))
+        self._accumulate(acc, fac, key)
+
+    def _closed_amplitude(self, ai, amp, args, acc, fac):
+        """An amplitude contracted at a vertex next to the root (Dag._reclose): every argument is an
+        explicit current, the root's among them."""
+        nd = self.em.dag.nodes
+        if amp.op == "vvvx":
+            x, y, v = amp.args
+            expr = (f"vvvxxx<R>({args[0]}, {self.qmom(nd[x].mask)}, {args[1]}, {self.qmom(nd[y].mask)}, "
+                    f"{args[2]}, {self.qmom(nd[v].mask)})")
+        elif amp.op == "ggggx":
+            expr = "ggggxx<R>(" + ", ".join(args) + ")"
+        else:
+            expr = f"iovxx0<R, {self.pat.hq[nd[amp.args[0]].end]}>({args[0]}, {args[1]}, {args[2]})"
+        self.flops += FLOPS[amp.op] + FLOPS["class_add"]
+        key = ("a", ai)
+        self.lines.append(f"  const cx<R> {self.name(key)} = {expr};")
+        self._def(key, SIZES[self.prec]["amp"])
+        for a in amp.args:
+            self._use(("c", a))
+        self._accumulate(acc, fac, key)
+
+    def _accumulate(self, acc, fac, key):
         an = self.name(key)
         if fac == 1:
             self.lines.append(f"  {acc}.re += double({an}.re); {acc}.im += double({an}.im);")
@@ -439,6 +474,8 @@ class Emitter:
     def _plan(self, pat: Pattern, prec: str):
         """Split the pattern's classes into register-bounded groups of amplitudes."""
         classes = colour_classes(self.vectors, pat.amps)
+        if PLAN == "greedy":
+            return classes, self._plan_greedy(pat, prec, classes)
         items = [(ci, ai, fac) for ci, (_, members) in enumerate(classes) for ai, fac in members]
         groups, cur = [], []
         budget = self.budget[prec]
@@ -455,6 +492,64 @@ class Emitter:
         if cur:
             groups.append(cur)
         return classes, groups
+
+    def _plan_greedy(self, pat: Pattern, prec: str, classes) -> list:
+        """Register-bounded groups of whole colour classes that share as many currents as possible.
+
+        A group starts from the first remaining class (first-seen order) and grows by the remaining
+        class whose amplitudes need the least arithmetic on top of the currents the group already
+        builds (the class's closure in the DAG minus the group's), until the simulated register
+        peak would exceed the budget.  Currents are recomputed only where two groups need them."""
+        nd = self.dag.nodes
+        root = self.dag.ext[self.proc.root]
+
+        def cost(x):
+            op = nd[x].op
+            return FLOPS["ext"] if op == "ext" else FLOPS[op]
+        closures = []
+        for _, members in classes:
+            seen, stack = set(), [root]
+            for ai, _ in members:
+                stack.extend(self.dag.amps[ai].args)
+            while stack:
+                x = stack.pop()
+                if x not in seen:
+                    seen.add(x)
+                    stack.extend(nd[x].args)
+            closures.append(seen)
+        users = {}
+        for ci, nodes in enumerate(closures):
+            for x in nodes:
+                users.setdefault(x, []).append(ci)
+        full = [sum(cost(x) for x in nodes) for nodes in closures]
+        remaining = set(range(len(classes)))
+        budget = self.budget[prec]
+        groups, pos = [], 0
+        while remaining:
+            while pos not in remaining:
+                pos += 1
+            need = {ci: full[ci] for ci in remaining}
+            have, cur = set(), []
+            g = _Group(self, pat, prec, 0)
+            cand = pos
+            while cand is not None:
+                items = [(cand, ai, fac) for ai, fac in classes[cand][1]]
+                for it in items:
+                    g.amplitude(it[1], "acc", it[2])
+                if cur and g.peak() > budget:
+                    break
+                cur.extend(items)
+                remaining.discard(cand)
+                del need[cand]
+                for x in closures[cand] - have:
+                    have.add(x)
+                    c = cost(x)
+                    for u in users[x]:
+                        if u in need:
+                            need[u] -= c
+                cand = min(need, key=lambda c: (need[c], c)) if need else None
+            groups.append(cur)
+        return groups
 
     def _build(self, pat, prec, items, gid):
         g = _Group(self, pat, prec, gid)
@@ -473,12 +568,18 @@ class Emitter:
                 last_group[ci] = gi
         built = [self._build(pat, prec, items, gi) for gi, items in enumerate(groups)]
         # chunks: consecutive groups, cut only where no colour class is open
+        nwave = self.nwave[prec]
+        if nwave > 1:
+            share = sum(b.flops for b in built) // (nwave * COOP_CHUNKS_PER_WAVE)
+            target = max(1, min(COOP_CHUNK_FLOPS[prec], share))
+        else:
+            target = CHUNK_FLOPS
         chunks, cur, cur_flops = [], [], 0
         for gi, b in enumerate(built):
             cur.append(gi)
             cur_flops += b.flops
             open_cls = any(last_group[c] > gi for c, _, _ in groups[gi])
-            if cur_flops >= (COOP_CHUNK_FLOPS[prec] if self.nwave[prec] > 1 else CHUNK_FLOPS) and not open_cls:
+            if cur_flops >= target and not open_cls:
                 chunks.append(cur)
                 cur, cur_flops = [], 0
         if cur:
@@ -503,10 +604,11 @@ class Emitter:
                     w(f"  const wsp<R> w{leg.index} = oxxxx0<R, {h[leg.index]}>(pl{leg.index});")
         out = []
         total_flops = 0
+        ext_flops = 0 if self.group_externals[prec] else FLOPS["ext"] * proc.n
         for ki, gis in enumerate(chunks):
-            lines = list(prologue)
+            lines = []
             w = lines.append
-            flops = 0 if self.group_externals[prec] else FLOPS["ext"] * proc.n
+            flops = 0
             for gi in gis:
                 items = groups[gi]
                 for ci in sorted({c for c, _, _ in items if min(g for g in range(len(groups))
@@ -528,9 +630,9 @@ class Emitter:
                             w(f"  yl[{a}][0][lane] += {_lit(sc)} * k{ci}.re; yl[{a}][1][lane] += {_lit(sc)} * k{ci}.im;")
             name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_c{ki}"
             src = (f"__device__ __noinline__ void {name}({self.chunk_params}) {{\n  using R = {prec};\n"
-                   + "\n".join(lines) + "\n}\n")
-            out.append([name, src, 0, flops, lines])
-            total_flops += flops
+                   + "\n".join(prologue + lines) + "\n}\n")
+            out.append([name, src, 0, flops + ext_flops, lines])
+            total_flops += flops + ext_flops
         nwave = self.nwave[prec]
         if nwave > 1:
             # longest chunk first onto the least loaded wave
@@ -539,23 +641,27 @@ class Emitter:
                 wv = min(range(nwave), key=lambda v: load[v])
                 c[2] = wv
                 load[wv] += c[3]
-        if MERGE_WAVE_CHUNKS > 1 and len(out) <= MERGE_MAX_PATTERN_CHUNKS:
-            # a wave's chunks in order, each in a scope of its own, merged into functions of up to
-            # MERGE_WAVE_CHUNKS chunks: fewer calls, fewer saves of callee-saved registers
+        if MERGE_WAVE_CHUNKS > 1 and total_flops <= MERGE_MAX_PATTERN_FLOPS:
+            # a wave's chunks in order, each in a scope of its own after one shared prologue, merged
+            # into functions of up to MERGE_WAVE_CHUNKS chunks: fewer calls, fewer saves of
+            # callee-saved registers, and the externals built once per call
             merged = []
+            total_flops = 0
             for v in range(nwave):
                 mine = [c for c in out if c[2] == v]
                 for m0 in range(0, len(mine), MERGE_WAVE_CHUNKS):
                     run = mine[m0:m0 + MERGE_WAVE_CHUNKS]
                     name = f"p{pi}_{'f64' if prec == 'double' else 'f32'}_w{v}_{m0 // MERGE_WAVE_CHUNKS}"
-                    body = []
+                    body = list(prologue)
                     for c in run:
                         body.append("  {")
                         body.extend(c[4])
                         body.append("  }")
                     src = (f"__device__ __noinline__ void {name}({self.chunk_params}) {{\n  using R = {prec};\n"
                            + "\n".join(body) + "\n}\n")
-                    merged.append([name, src, v, sum(c[3] for c in run), body])
+                    fl = sum(c[3] - ext_flops for c in run) + ext_flops
+                    merged.append([name, src, v, fl, body])
+                    total_flops += fl
             out = merged
         cflops = total_flops + 2 * self.kdim * (self.kdim + 1)
         self.flops[prec] += cflops * pat.ncfg

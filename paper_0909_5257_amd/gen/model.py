@@ -28,6 +28,8 @@ from typing import Optional
 from . import colour_algebra as ca
 
 FLAVOURS = ("g", "u", "u~")
+# evaluate diagrams at the vertex next to the root where that saves a current (Dag._reclose)
+RECLOSE = False
 
 
 @dataclasses.dataclass(frozen=True)
@@ -168,6 +170,8 @@ class Dag:
         self.amps: list[Amp] = []
         self._close(rest, kinds[root])
         self._basis_and_coefficients()
+        if RECLOSE:
+            self._reclose()
 
     # ---------------------------------------------------------------- build
     def _ext_colour(self, leg):
@@ -273,6 +277,86 @@ class Dag:
                         self.amps.append(Amp("iov", (f, v), col, nd[f].pairs + nd[v].pairs + ((nd[f].end, root),)))
         else:
             raise NotImplementedError("root leg must be a gluon or a flowing-out quark")
+
+    # ---------------------------------------------------------------- closing vertex
+    def _reclose(self):
+        """Evaluate each diagram at the vertex next to the root where that saves a current.
+
+        A diagram's amplitude is the same number whichever of its vertices the currents are
+        contracted at; only the currents needed differ.  With a quark root every diagram is
+        iov(F, root, J).  If F = fvi(F', G) is built for this diagram alone, the amplitude is taken
+        at F's vertex instead: iovx(F', O, G) with O = fvo(root, J), the root line continued
+        through J, which all diagrams with the same J share.  Otherwise, if J is built for this
+        diagram alone, at J's vertex: with V = jio(F, root) (the current of the pair F, root,
+        shared by all diagrams with the same F), jvv(X, Y) becomes vvvx(X, Y, V), a jggg piece
+        (X, Y, Z) becomes ggggx(X, Y, Z, V) and jio(F'', O'') becomes iovx(F'', O'', V).  Colour
+        factors and signs stay those of the diagram; the propagator between the two vertices
+        moves from the expanded current into O or V (same invariant).  With a gluon root,
+        four-gluon diagrams keep the root closure; a three-gluon diagram vvv(A, B, W) with W the
+        root gluon and B (or A) built for it alone is taken at B's vertex with V = jvv(W, A) (or
+        jvv(B, W)), which the cyclic, antisymmetric three-gluon vertex makes equal.  Unused
+        currents are dropped and the rest renumbered."""
+        nd = self.nodes
+        root_ext = self.ext[self.proc.root]
+        use = {}
+        for node in nd:
+            for a in node.args:
+                use[a] = use.get(a, 0) + 1
+        for amp in self.amps:
+            for a in amp.args:
+                use[a] = use.get(a, 0) + 1
+        made = {}
+
+        def derived(key, build):
+            if key not in made:
+                made[key] = build().id
+            return made[key]
+        expand = {"jvv": "vvvx", "jggg": "ggggx"}
+        for amp in self.amps:
+            if amp.op == "vvv":
+                a, b = amp.args
+                if nd[b].op in expand and use[b] == 1:
+                    # vvv(A, B, W) = V . B with V = jvv(W, A) (cyclic three-gluon vertex)
+                    v = derived(("jvv", root_ext, a), lambda: self._jvv(root_ext, a))
+                    amp.op, amp.args = expand[nd[b].op], tuple(nd[b].args) + (v,)
+                elif nd[a].op in expand and use[a] == 1:
+                    # vvv(A, B, W) = V . A with V = jvv(B, W)
+                    v = derived(("jvv", b, root_ext), lambda: self._jvv(b, root_ext))
+                    amp.op, amp.args = expand[nd[a].op], tuple(nd[a].args) + (v,)
+                continue
+            if amp.op != "iov":
+                continue
+            f, j = amp.args
+            if nd[f].op == "fvi" and use[f] == 1:
+                fp, g = nd[f].args
+                o = derived(("fvo", j), lambda: self._fvo(root_ext, j))
+                amp.op, amp.args = "iovx", (fp, o, g)
+            elif nd[j].op in ("jvv", "jggg", "jio") and use[j] == 1:
+                v = derived(("jio", f), lambda: self._jio(f, root_ext))
+                inner = nd[j].args
+                amp.op = {"jvv": "vvvx", "jggg": "ggggx", "jio": "iovx"}[nd[j].op]
+                amp.args = tuple(inner) + (v,)
+        # keep the currents the amplitudes reach, in their order of creation
+        live, stack = set(self.ext.values()), [a for amp in self.amps for a in amp.args]
+        while stack:
+            x = stack.pop()
+            if x not in live:
+                live.add(x)
+                stack.extend(self.nodes[x].args)
+        remap = {}
+        kept = []
+        for node in self.nodes:
+            if node.id in live:
+                remap[node.id] = len(kept)
+                kept.append(node)
+        for node in kept:
+            node.id = remap[node.id]
+            node.args = tuple(remap[a] for a in node.args)
+        for amp in self.amps:
+            amp.args = tuple(remap[a] for a in amp.args)
+        self.ext = {leg: remap[i] for leg, i in self.ext.items()}
+        self.nodes = kept
+        self.by_key = {}
 
     # ---------------------------------------------------------------- colour
     def _basis_and_coefficients(self):

@@ -107,7 +107,14 @@ def test_colour_vectors_match_oracle_amplitudes(torch_dev, spec):
          f"{proc.n_colours}: max |y - c M J| / |y|max {rel.max():.3e}; |c| g^(n-2) in "
          f"[{(np.abs(c[big]) * g ** (n_ext - 2)).min():.15f}, {(np.abs(c[big]) * g ** (n_ext - 2)).max():.15f}]")
     assert rel.max() <= 1e-12
-    assert np.allclose(np.abs(c[big]) * g ** (n_ext - 2), 1.0, rtol=1e-12, atol=0)
+    # |c| g^(n-2) = 1: a least-squares constant is off by at most the residual over the vector's own
+    # norm, so small configurations of an event carry a proportionally looser bound
+    own = np.linalg.norm(y, axis=2)
+    dev = np.abs(np.abs(c) * g ** (n_ext - 2) - 1.0)
+    bound = 1e-12 + 2.0 * resid / np.maximum(own, 1e-300)
+    _say(f"[jamp] {spec}: max ||c| g^(n-2) - 1| {dev[big].max():.3e}, max of it over its bound "
+         f"{(dev[big] / bound[big]).max():.3f}")
+    assert np.all(dev[big] <= bound[big])
     # per-helicity colour sums: y^H W y g^(2(n-2)) against J^H N J
     q = np.einsum("nsa,ab,nsb->ns", y.conj(), wmat, y).real * g ** (2 * (n_ext - 2))
     qo = colour_sum(jo, colour_data(spec).N).T                          # [N, S]
