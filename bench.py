@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("fb662da97a82d942", 409368),
-    ("g g > g g g g", "fp64"): ("eed2264c1b4a5d30", 52980),
-    ("u u~ > g g g g g", "mixed"): ("985390c88536bfa7", 419847),
-    ("g g > g g g g", "mixed"): ("18bf562c3869fcf4", 161415),
+    ("u u~ > g g g g g", "fp64"): ("e2b5b34c8916fd2c", 366282),
+    ("g g > g g g g", "fp64"): ("e3803aa1193c0767", 84736),
+    ("u u~ > g g g g g", "mixed"): ("d28ecbfbe1d5ff5f", 300470),
+    ("g g > g g g g", "mixed"): ("c6942e1fec661fd2", 91574),
 }
 
 
@@ -417,7 +417,8 @@ def helicity_mc_run(torch, workload, dev_inputs, steps, warmup):
 
 
 def colour_gemm_run(torch, rows, steps, warmup):
-    """Colour quadratic form of g g > g g g g (K = 120) as a GEMM over rows (event, helicity) in three modes."""
+    """Colour quadratic form of g g > g g g g (K = 120) over rows (event, helicity): float64, float32 and
+    bf16x3 on the matrix cores and float64 on the vector ALUs, with the fraction of the HBM roofline."""
     from paper_0909_5257_amd.heget import Process, colour_quadratic_form
     _, _, nval = Process("g g > g g g g", "fp64").color_matrix()
     k = nval.shape[0]
@@ -425,14 +426,19 @@ def colour_gemm_run(torch, rows, steps, warmup):
     g = torch.Generator(device="cuda")
     g.manual_seed(0)
     jamp = torch.randn((rows, 2, k), dtype=torch.float64, device="cuda", generator=g)
-    q = {m: torch.empty(rows, dtype=torch.float64, device="cuda") for m in ("fp64", "fp32", "bf16x3")}
+    q = {m: torch.empty(rows, dtype=torch.float64, device="cuda") for m in ("fp64", "fp32", "bf16x3", "fp64_valu")}
     res = {"rows": rows, "colours": k, "shape": f"[{2 * rows} x {k}] . [{k} x {k}] + row dot"}
     flops = 2.0 * (2 * rows) * k * k + 2.0 * (2 * rows) * k
     for m in q:
         ms = _timed(torch, lambda: colour_quadratic_form(nmat, jamp, m, out=q[m]), steps, warmup)
         res[m] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12}
-    for m in ("fp32", "bf16x3"):
+    for m in ("fp32", "bf16x3", "fp64_valu"):
         res[m]["max_rel_err_vs_fp64"] = float(((q[m] - q["fp64"]).abs() / q["fp64"].abs()).max())
+    # HBM roofline of the contraction: J read once (16 K bytes per row) and q written (8 bytes per row)
+    hbm = rows * (16 * k + 8)
+    for m in q:
+        res[m]["hbm_gbs"] = hbm / (res[m]["ms"] * 1e-3) / 1e9
+        res[m]["frac_of_hbm_peak"] = res[m]["hbm_gbs"] / 8000.0
     log(f"[bench] colour GEMM K={k} rows={rows}: " + ", ".join(f"{m} {res[m]['ms']:.2f} ms" for m in q))
     del jamp
     return res

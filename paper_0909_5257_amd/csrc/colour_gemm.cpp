@@ -280,39 +280,54 @@ __global__ __launch_bounds__(64 * kWaves) void qf_mfma_bf16x3(int k, const doubl
   }
 }
 
-// float64 on the vector ALUs: a workgroup stages 64 real rows transposed in LDS (one per lane);
-// wave w takes the 8-colour row blocks w, w + 4, ... of the symmetric form
-// q_t = sum_a x_ta (N_aa x_ta + 2 sum_{b > a} N_ab x_tb), N read with wave-uniform scalar loads.
+// float64 on the vector ALUs.  The symmetric weights of q_t = sum_a x_ta (N_aa x_ta + 2 sum_{b > a}
+// N_ab x_tb) are staged in LDS once per workgroup, in 8-row blocks j laid out as [b - 8 j][8] for
+// b >= 8 j (the upper block triangle, 0 below the diagonal and outside K x K), so each wave reads 8
+// consecutive weights with broadcast loads.  The workgroup stages 64 real rows transposed in LDS (one
+// per lane); the row blocks are dealt to the waves in the order 0, 1, ..., W-1, W-1, ..., 0, W, ...
+// (their lengths fall with the block index).
+constexpr int kValuW = (kMaxK / 8) * 8 * kMaxK - 8 * 8 * (kMaxK / 8) * (kMaxK / 8 - 1) / 2;   // doubles
+
 __global__ __launch_bounds__(64 * kWaves) void qf_valu_f64(int k, const double* __restrict__ nmat,
                                                            const double* __restrict__ x, int64_t nreal,
                                                            double* __restrict__ q) {
   __shared__ double xs[kMaxK][64];
+  __shared__ double wl[kValuW];
   __shared__ double part[kWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kp = (k + 7) & ~7;
+  const int nblk = kp >> 3;
+  // block j starts at 8 * sum_{j' < j} (kp - 8 j') = 8 j kp - 32 j (j - 1)
+  for (int j = 0; j < nblk; ++j) {
+    const int off = 8 * j * kp - 32 * j * (j - 1), len = 8 * (kp - 8 * j);
+    for (int e = threadIdx.x; e < len; e += 64 * kWaves) {
+      const int a = 8 * j + (e & 7), b = 8 * j + (e >> 3);
+      wl[off + e] = (a < k && b < k && b >= a) ? (b == a ? 1.0 : 2.0) * nmat[(int64_t)a * k + b] : 0.0;
+    }
+  }
   const int64_t ntiles = (nreal + 63) >> 6;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * 64;
     const int64_t nrow = nreal - r0 < 64 ? nreal - r0 : 64;
     const double* src = x + r0 * k;
-    for (int e = threadIdx.x; e < 64 * kp; e += 64 * kWaves) {
-      const int t = e / kp, c = e - t * kp;
-      xs[c][t] = (t < nrow && c < k) ? src[(int64_t)t * k + c] : 0.0;
-    }
+    // wave w copies rows w, w + W, ...: its lanes read consecutive colours of one row
+    for (int t = wave; t < 64; t += kWaves)
+      for (int c = lane; c < kp; c += 64) xs[c][t] = (t < nrow && c < k) ? src[(int64_t)t * k + c] : 0.0;
     __syncthreads();
     double acc = 0.0;
-    for (int a0 = 8 * wave; a0 < k; a0 += 8 * kWaves) {
+    for (int j = 0; j < nblk; ++j) {
+      const int round = j / kWaves, pos = j - round * kWaves;
+      if ((round & 1 ? kWaves - 1 - pos : pos) != wave) continue;
+      const int a0 = 8 * j;
+      const double* wj = wl + 8 * j * kp - 32 * j * (j - 1);
       double tr[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) tr[i] = 0.0;
-      for (int b = a0; b < k; ++b) {
+      for (int b = a0; b < kp; ++b) {
         const double xb = xs[b][lane];
+        const double* wb = wj + 8 * (b - a0);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int a = a0 + i;
-          const double w = (a < k && b >= a) ? (b == a ? 1.0 : 2.0) * nmat[(int64_t)a * k + b] : 0.0;
-          tr[i] += w * xb;
-        }
+        for (int i = 0; i < 8; ++i) tr[i] += wb[i] * xb;
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) acc += xs[a0 + i][lane] * tr[i];

@@ -89,23 +89,36 @@ template <> HD double inv_msq<double>(const mom4<double>& p) {
 
 // ------------------------------------------------------------ external states
 
-// Polarisation of a massless gluon with physical momentum p and helicity lam.
-// outgoing = true returns the complex conjugate.
+// 1/sqrt(x) for x > 0: the hardware estimate, in float64 refined by two Newton-Raphson steps
+// y <- y (3 - x y^2) / 2 (each squares the relative error).
+HD float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+HD double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * __builtin_fma(-h * y, y, 1.5);
+  y = y * __builtin_fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Polarisation of a massless gluon with physical momentum p and helicity lam, computed in the
+// precision of the result (R).  outgoing = true returns the complex conjugate.
 template <class R> HD vec4<R> vxxxx0(const mom4<double>& p, int lam, bool outgoing) {
-  double pt2 = p.x * p.x + p.y * p.y;
-  double pabs = sqrt(pt2 + p.z * p.z);
-  double pt = sqrt(pt2);
-  double ct = p.z / pabs, st = pt / pabs;
-  double cf = pt > 0.0 ? p.x / pt : 1.0;
-  double sf = pt > 0.0 ? p.y / pt : 0.0;
-  const double r2 = 0.70710678118654752440;
-  double l = lam > 0 ? r2 : -r2;
-  double im_sign = outgoing ? -r2 : r2;
+  const R px = R(p.x), py = R(p.y), pz = R(p.z);
+  const R pt2 = px * px + py * py;
+  const R ipa = rsq(pt2 + pz * pz);
+  const bool side = pt2 > R(0);
+  const R ipt = side ? rsq(pt2) : R(0);
+  const R ct = pz * ipa, st = pt2 * ipt * ipa;
+  const R cf = side ? px * ipt : R(1);
+  const R sf = side ? py * ipt : R(0);
+  const R r2 = R(0.70710678118654752440);
+  const R l = lam > 0 ? r2 : -r2;
+  const R im_sign = outgoing ? -r2 : r2;
   vec4<R> e;
   e.c0 = {R(0), R(0)};
-  e.c1 = {R(-l * ct * cf), R(im_sign * sf)};
-  e.c2 = {R(-l * ct * sf), R(-im_sign * cf)};
-  e.c3 = {R(l * st), R(0)};
+  e.c1 = {-l * ct * cf, im_sign * sf};
+  e.c2 = {-l * ct * sf, -im_sign * cf};
+  e.c3 = {l * st, R(0)};
   return e;
 }
 
@@ -125,12 +138,12 @@ template <class R> HD vec4<R> vxxxx0g(const mom4<double>& p, int lam, bool outgo
   return vxxxx0<R>(p, lam, outgoing);
 }
 
-// sqrt(2E) xi_h(p) for a massless momentum
+// sqrt(2E) xi_h(p) for a massless momentum (float64 inputs, result in R)
 template <class R, int H> HD wsp<R> weyl_xi(const mom4<double>& p) {
   double rho = p.e + p.z;
   wsp<R> w;
   if (rho > 1e-10 * p.e) {
-    double sr = sqrt(rho), isr = 1.0 / sr;
+    const double isr = rsq(rho), sr = rho * isr;
     if (H > 0) {
       w.s0 = {R(sr), R(0)};
       w.s1 = {R(p.x * isr), R(p.y * isr)};
@@ -139,7 +152,7 @@ template <class R, int H> HD wsp<R> weyl_xi(const mom4<double>& p) {
       w.s1 = {R(sr), R(0)};
     }
   } else {
-    double s2e = sqrt(2.0 * p.e);
+    const double s2e = 2.0 * p.e * rsq(2.0 * p.e);
     if (H > 0) {
       w.s0 = {R(0), R(0)};
       w.s1 = {R(s2e), R(0)};

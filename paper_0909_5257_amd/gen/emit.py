@@ -221,6 +221,16 @@ class _Group:
         key = ("P", mask)
         if key not in self.defs:
             proc = self.em.proc
+            root_bit = 1 << proc.root
+            if mask & root_bit and mask != root_bit:
+                # a current through the root leg (closing vertex moved inwards): its momentum is minus
+                # that of the complementary legs, taken that way so that every propagator invariant is
+                # formed from the same legs as in a root-closed evaluation (same rounding)
+                rest = ((1 << proc.n) - 1) ^ mask
+                self.lines.append(f"  const mom4<double> {self.name(key)} = neg({self.psum(rest)});")
+                self._def(key, SIZES[self.prec]["P"])
+                self._use(key)
+                return self.name(key)
             bits = [i for i in range(proc.n) if mask >> i & 1]
             if len(bits) == 1:
                 i = bits[0]

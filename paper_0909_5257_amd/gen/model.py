@@ -29,7 +29,7 @@ from . import colour_algebra as ca
 
 FLAVOURS = ("g", "u", "u~")
 # evaluate diagrams at the vertex next to the root where that saves a current (Dag._reclose)
-RECLOSE = False
+RECLOSE = True
 
 
 @dataclasses.dataclass(frozen=True)
