@@ -245,3 +245,26 @@ def test_reduction_map_and_slot_table(spec):
         assert h & 1                                  # leg 0 at +1
         pi = int(np.searchsorted(offsets, s, side="right") - 1)
         assert hmap[h] == (pi << 16) | (s - offsets[pi])
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g g", "u u~ > g g g g", "u u > u u g g", "u g > u g g g"])
+def test_greedy_plan_covers_every_amplitude_once(spec):
+    """The register plan: every active amplitude of a pattern lands in exactly one group, each colour
+    class stays within one group, and a group exceeds the register budget only if it holds a single
+    class (a class is never split)."""
+    from paper_0909_5257_amd.gen import emit as E
+    dag = Dag(parse(spec))
+    em = Emitter(dag, dag.colour_matrix())
+    for pat in em.pats:
+        for prec in ("double", "float"):
+            classes, groups = em._plan(pat, prec)
+            items = [it for g in groups for it in g]
+            assert sorted(ai for _, ai, _ in items) == sorted(pat.amps)
+            home = {}
+            for gi, g in enumerate(groups):
+                for ci, _, _ in g:
+                    assert home.setdefault(ci, gi) == gi
+                built = E._Group(em, pat, prec, 0)
+                for _, ai, fac in g:
+                    built.amplitude(ai, "acc", fac)
+                assert built.peak() <= em.budget[prec] or len({ci for ci, _, _ in g}) == 1
