@@ -100,20 +100,22 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Share of the colour quadratic form computed by one of W waves, for a colour
-// vector held in LDS as yl[a][0|1][lane]: the wave takes row blocks
-// blk = wave, wave + W, ...  The table holds
-// M_ab = W_ab (b > a), W_aa / 2 (b = a), 0 (b < a) in blocks of B rows laid
-// out as [K/B][K][B] so that the B row values of one column are contiguous
-// and wave-uniform (scalar loads).  Result: 2 sum over the wave's rows of
-// sum_b M_ab (Re y_a Re y_b + Im y_a Im y_b).
-template <int K, int B, int W>
-__device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int lane, int wave,
+// Share of the colour quadratic form computed by one wave, for a colour vector held in LDS as
+// yl[a][0|1][lane]: the wave takes the row blocks listed in blocks (blocks[0] = their count; the
+// generator deals the blocks of the upper triangle to the waves longest first).  The table holds
+// M_ab = W_ab (b > a), W_aa / 2 (b = a), 0 (b < a) in blocks of B rows laid out as [K/B][K][B] so that
+// the B row values of one column are contiguous and wave-uniform (scalar loads).  The column loop is
+// unrolled by 8 so that the loads of eight columns are in flight together.  Result: 2 sum over the
+// wave's rows of sum_b M_ab (Re y_a Re y_b + Im y_a Im y_b).
+template <int K, int B>
+__device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int lane, const int* __restrict__ blocks,
                                                       const double* __restrict__ cmat) {
   static_assert(K % B == 0, "colour block must divide the colour dimension");
   double q = 0.0;
+  const int nblk = blocks[0];
 #pragma unroll 1
-  for (int blk = wave; blk < K / B; blk += W) {
+  for (int i = 1; i <= nblk; ++i) {
+    const int blk = blocks[i];
     const int a0 = blk * B;
     const double* m = cmat + (int64_t)blk * K * B;
     double tr[B], ti[B];
@@ -122,7 +124,7 @@ __device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int l
       tr[a] = 0.0;
       ti[a] = 0.0;
     }
-#pragma unroll 2
+#pragma unroll 8
     for (int b = a0; b < K; ++b) {
       const double jr = yl[b][0][lane], ji = yl[b][1][lane];
 #pragma unroll

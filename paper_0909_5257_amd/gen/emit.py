@@ -406,13 +406,34 @@ class Emitter:
         self.budget = {prec: tuned[prec].get("budget", GROUP_BUDGET[prec]) for prec in tuned}
         self.target_waves = {prec: tuned[prec].get("waves_per_cu", TARGET_WAVES_PER_CU[prec]) for prec in tuned}
         self.nwave = {prec: self.waves_per_workgroup(prec) for prec in ("double", "float")}
-        # colour-sum row blocks: the largest block size that still gives every wave two blocks
+        # colour-sum row blocks: the block size (a divisor of K') whose longest-first assignment to the
+        # waves is best balanced (blocks of the upper triangle shrink with the row), larger on ties
         most = max(self.nwave.values())
         divs = [b for b in (8, 6, 4, 3, 2, 1) if self.kdim % b == 0]
-        self.cblock = next((b for b in divs if most == 1 or self.kdim // b >= 2 * most), divs[-1])
+        self.cblock = min(divs, key=lambda b: (round(self._block_owners(b, most)[1], 3), -b))
         self.flops = {"double": 0, "float": 0}
         self.algo_flops = 0
         self.stats = {}
+
+    def _block_owners(self, bsz: int, nwave: int):
+        """Longest-first assignment of the colour-sum row blocks (block j spans K' - bsz j columns of
+        the upper triangle) to nwave waves: (owner of each block, max load / mean load)."""
+        load, owner = [0] * nwave, []
+        for j in range(self.kdim // bsz):
+            wv = min(range(nwave), key=lambda v: load[v])
+            owner.append(wv)
+            load[wv] += self.kdim - bsz * j
+        return owner, max(load) * nwave / sum(load)
+
+    def block_table(self, prec: str) -> str:
+        """__constant__ table of the row blocks each wave sums: [wave][0] = count, then the blocks."""
+        nwave = self.nwave[prec]
+        owner, _ = self._block_owners(self.cblock, nwave)
+        rows = [[j for j, o in enumerate(owner) if o == v] for v in range(nwave)]
+        width = 1 + max(len(r) for r in rows)
+        name = f"CSB_{'F64' if prec == 'double' else 'F32'}"
+        body = ", ".join("{" + ", ".join(str(x) for x in [len(r)] + r + [0] * (width - 1 - len(r))) + "}" for r in rows)
+        return f"__constant__ int {name}[{nwave}][{width}] = {{{body}}};"
 
     def gluon_ext(self, pl: str, lam: str, leg) -> str:
         """Expression of one external gluon polarisation (physical momentum pl, helicity lam)."""
@@ -830,7 +851,8 @@ class Emitter:
                 w("        dst[2 * a + 1] = yl[a][1][lane];")
                 w("      }")
                 w("    }")
-            part = f"colour_sum_lds_part<{self.kdim}, {self.cblock}, {nwave}>(yl, lane, wave, cmat)"
+            part = (f"colour_sum_lds_part<{self.kdim}, {self.cblock}>(yl, lane, "
+                    f"&CSB_{'F64' if prec == 'double' else 'F32'}[wave][0], cmat)")
             if sampled:
                 w(f"    const double part = {part};")
                 w(f"    if (my_pat == {pi}) q += part;")
@@ -883,6 +905,8 @@ class Emitter:
         if with_hmap:
             lines.append(f"__constant__ int HMAP[{1 << proc.n}] = {{"
                          + ", ".join(str(x) for x in self.helicity_map()) + "};")
+        lines.append("// colour-sum row blocks of each wave: count, then block indices")
+        lines += [self.block_table("double"), self.block_table("float")]
         return lines
 
     def emit_hook(self) -> str:
