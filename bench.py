@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("eef35cb00d3257f0", 366307),
-    ("g g > g g g g", "fp64"): ("ceb9e8ab34352426", 84735),
-    ("u u~ > g g g g g", "mixed"): ("c5c387ac7bb6ae1c", 300347),
-    ("g g > g g g g", "mixed"): ("73d82f4ce2c439f8", 91545),
+    ("u u~ > g g g g g", "fp64"): ("d20b3b6ffc597e46", 293),
+    ("g g > g g g g", "fp64"): ("bd2fc1b73fc41898", 203),
+    ("u u~ > g g g g g", "mixed"): ("1c56735aedf68d3b", 27984),
+    ("g g > g g g g", "mixed"): ("40320e9696b61733", 18339),
 }
 
 

@@ -77,6 +77,10 @@ __device__ __forceinline__ void opaque_copy(const double (&pm)[NEXT][4], double 
 // wavefunctions (eps^0, Im eps^3) are passed through unchanged.
 __device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ int opaque_int(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 __device__ __forceinline__ mom4<double> fresh(const mom4<double>& p) {
   mom4<double> q = p;

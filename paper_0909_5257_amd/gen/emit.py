@@ -58,6 +58,18 @@ FORCE_WAVES = 0           # if non-zero, waves per workgroup for every process a
 # minutes).
 MERGE_WAVE_CHUNKS = 16
 MERGE_MAX_PATTERN_FLOPS = 1_500_000
+# The summed kernel runs, per pattern, one loop over the helicity configurations inside each wave's
+# branch (clear the colour vector, the wave's diagram work, its colour-sum share, with the workgroup
+# barriers between them), with the wave's work inlined when it is one merged function: no call per
+# configuration, so no save and restore of callee-saved registers per configuration.  The loop lives
+# in the kernel, not in a called function: a loop around a body of several hundred KB needs long
+# branches, and in a called function those have been compiled with the return-address registers as
+# their scratch pair.  Each iteration passes the lane index through an opaque copy, so the LDS
+# addresses of the colour-vector rows are formed inside the loop instead of being hoisted out of it
+# and spilled (measured: the float64 u u~ > 5g kernel then needs no scratch at all).  The
+# sampled-helicity and test-hook kernels call the chunk functions; a tuned setting "calls" keeps one
+# call per configuration in the summed kernel too.
+WAVE_LOOP = True
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 # How amplitudes are packed into register groups: "greedy" (whole colour classes, each group grown by
 # the class that shares the most currents with it) or "classes" (first-seen class order, cut anywhere).
@@ -405,6 +417,7 @@ class Emitter:
         self.group_externals = {prec: tuned[prec].get("externals") == "group" for prec in tuned}
         self.budget = {prec: tuned[prec].get("budget", GROUP_BUDGET[prec]) for prec in tuned}
         self.target_waves = {prec: tuned[prec].get("waves_per_cu", TARGET_WAVES_PER_CU[prec]) for prec in tuned}
+        self.kernel_loop = {prec: WAVE_LOOP and not hook and not tuned[prec].get("calls", False) for prec in tuned}
         self.nwave = {prec: self.waves_per_workgroup(prec) for prec in ("double", "float")}
         # colour-sum row blocks: the block size (a divisor of K') whose longest-first assignment to the
         # waves is best balanced (blocks of the upper triangle shrink with the row), larger on ties
@@ -823,6 +836,29 @@ class Emitter:
         slot0 = 0
         nslots = sum(p.ncfg for p in self.pats)
         for pi, (pat, chunks) in enumerate(zip(self.pats, chunks_per_pattern)):
+            if self.kernel_loop[prec] and not sampled:
+                for v in range(nwave):
+                    names = [c[0] for c in chunks if c[2] == v]
+                    if len(names) == 1:
+                        names = [names[0] + "_i"]
+                    cond = ("if" if v == 0 else "} else if") + f" (wave == {v}) {{" if nwave > 1 else "{"
+                    w(f"  {cond}")
+                    w("#pragma unroll 1")
+                    w(f"    for (int cfg = 0; cfg < {pat.ncfg}; ++cfg) {{")
+                    # the lane index through an opaque copy: the LDS addresses derived from it are
+                    # formed inside the loop, not hoisted out of it and kept (or spilled) for good
+                    w("      const int ln = opaque_int(lane);")
+                    w(f"      for (int a = threadIdx.x; a < {self.kdim * 128}; a += {nt}) (&yl[0][0][0])[a] = 0.0;")
+                    w("      __syncthreads();")
+                    for nm in names:
+                        w(f"      {nm}(cfg, ln);")
+                    w("      __syncthreads();")
+                    w(f"      q += colour_sum_lds_part<{self.kdim}, {self.cblock}>(yl, ln, "
+                      f"&CSB_{'F64' if prec == 'double' else 'F32'}[{v}][0], cmat);")
+                    w("      __syncthreads();")
+                    w("    }")
+                w("  }")
+                continue
             if sampled:
                 w(f"  if (__syncthreads_or(my_pat == {pi})) {{")
                 w(f"    const int cfg = my_pat == {pi} ? my_cfg : 0;")
@@ -973,6 +1009,10 @@ class Emitter:
             for pat_chunks in chunks[prec]:
                 for c in pat_chunks:
                     lines.append(c[1])
+                    if self.kernel_loop[prec] and sum(1 for d in pat_chunks if d[2] == c[2]) == 1:
+                        # the wave's only function: an inlined copy for the summed kernel's loop
+                        lines.append(c[1].replace(f"__device__ __noinline__ void {c[0]}(",
+                                                  f"__device__ __forceinline__ void {c[0]}_i(", 1))
             w("}  // namespace")
             lines.extend(self._kernel(prec, chunks[prec]))
             lines.extend(self._kernel(prec, chunks[prec], sampled=True))

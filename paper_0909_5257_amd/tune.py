@@ -35,6 +35,9 @@ CANDIDATES = {
     "keep160": {"double": {"budget": 160}, "float": {"budget": 160}},
     "keep200": {"double": {"budget": 192}, "float": {"budget": 200}},
     "keep224": {"double": {"budget": 224}, "float": {"budget": 224}},
+    # the same with one call of the wave's work per helicity configuration instead of the loop inlined
+    # into the kernel (fewer registers spilled inside the loop where the inlined body spills)
+    "keep224c": {"double": {"budget": 224, "calls": True}, "float": {"budget": 224, "calls": True}},
     # one wave per 64-event group where the colour vector is small enough: no cross-wave
     # accumulation, bit-reproducible results
     "group176s": {"double": {"externals": "group", "budget": 176},

@@ -215,6 +215,38 @@ def test_committed_tuned_table_is_valid():
     for (spec, prec), s in TUNED.items():
         assert spec in PROCESSES and prec in ("double", "float")
         assert s.get("externals") in (None, "group") and 64 <= s.get("budget", 176) <= 512
+        assert s.get("calls") in (None, True)
+
+
+def _functions(src):
+    """(qualifier, name, body) of every device function and kernel in a generated source."""
+    out = []
+    for m in re.finditer(r"^(__device__ __noinline__|__device__ __forceinline__|__global__[^\n]*?) "
+                         r"(?:void|double) (\w+)\([^\n]*\) \{$", src, re.M):
+        end = src.index("\n}\n", m.end())
+        out.append((m.group(1), m.group(2), src[m.end():end]))
+    return out
+
+
+@pytest.mark.parametrize("spec", ["g g > g g g g", "u u > u u g", "u u~ > g g g g"])
+def test_called_functions_hold_no_loop(spec):
+    """Generated code structure: the helicity loop of the summed kernel lives in the kernel.  No
+    called (noinline) function contains a loop, so no called function needs the long branches
+    around a body of several hundred KB that have been compiled with the return-address registers
+    as scratch; where a wave's work is one function the summed kernel inlines it."""
+    dag = Dag(parse(spec))
+    srcs = Emitter(dag, dag.colour_matrix()).emit(with_hook=True)
+    srcs["hook"] = Emitter(dag, dag.colour_matrix(), hook=True).emit_hook()
+    for part, src in srcs.items():
+        src = src if isinstance(src, str) else "\n".join(src)
+        fns = _functions(src)
+        called = [b for q, n, b in fns if q == "__device__ __noinline__"]
+        assert called
+        assert not any(re.search(r"\b(for|while)\s*\(", b) for b in called)
+        if part != "hook":
+            me2 = [b for q, n, b in fns if n.startswith("me2_")]
+            assert len(me2) == 1 and "#pragma unroll 1\n    for (int cfg" in me2[0]
+            assert not any(re.search(rf"\b{n}\(", me2[0]) for q, n, b in fns if q == "__device__ __noinline__")
 
 
 @pytest.mark.parametrize("spec", ["g g > g g g", "g g > g g g g", "u u~ > g g g g", "u u > u u g", "u u > u u g g",
