@@ -54,6 +54,16 @@ template <class R> HD cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
 template <class R> HD vec4<R> operator+(const vec4<R>& a, const vec4<R>& b) {
   return {a.c0 + b.c0, a.c1 + b.c1, a.c2 + b.c2, a.c3 + b.c3};
 }
+template <class R> HD vec4<R> operator-(const vec4<R>& a, const vec4<R>& b) {
+  return {a.c0 - b.c0, a.c1 - b.c1, a.c2 - b.c2, a.c3 - b.c3};
+}
+template <class R> HD wsp<R> operator+(const wsp<R>& a, const wsp<R>& b) { return {a.s0 + b.s0, a.s1 + b.s1}; }
+template <class R> HD wsp<R> operator-(const wsp<R>& a, const wsp<R>& b) { return {a.s0 - b.s0, a.s1 - b.s1}; }
+// a + s b for a real factor s (operand sums of a closing vertex)
+template <class R> HD vec4<R> lin(const vec4<R>& a, R s, const vec4<R>& b) {
+  return {a.c0 + s * b.c0, a.c1 + s * b.c1, a.c2 + s * b.c2, a.c3 + s * b.c3};
+}
+template <class R> HD wsp<R> lin(const wsp<R>& a, R s, const wsp<R>& b) { return {a.s0 + s * b.s0, a.s1 + s * b.s1}; }
 template <class R> HD vec4<R> scale(cx<R> s, const vec4<R>& a) {
   return {s * a.c0, s * a.c1, s * a.c2, s * a.c3};
 }

@@ -36,6 +36,8 @@ FLOPS = {   # real floating-point operations per call, counted from the routines
     "vvv": 166, "gggg": 134, "iov": 58, "vvvx": 166, "ggggx": 134, "iovx": 58,
     "jvv": 156, "jggg": 120, "jio": 64, "fvi": 74, "fvo": 74,
     "ext": 40, "psum": 4, "inv": 8, "class_add": 4, "jamp_add": 4,
+    # sum of two operands of a closing vertex (vector / spinor), plain or with a rational factor
+    "sum_V": 8, "sum_W": 4, "lin_V": 16, "lin_W": 8,
 }
 
 CHUNK_FLOPS = 40000     # arithmetic per lane and configuration in one chunk function
@@ -70,6 +72,10 @@ MERGE_MAX_PATTERN_FLOPS = 1_500_000
 # sampled-helicity and test-hook kernels call the chunk functions; a tuned setting "calls" keeps one
 # call per configuration in the summed kernel too.
 WAVE_LOOP = True
+# Diagrams of one colour class that share all operands of their closing vertex but one, and whose
+# differing operands cover the same external legs (so carry the same momentum), are contracted once
+# with the sum of those operands: the vertex is linear in each operand current.
+MERGE_OPERANDS = True
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 # How amplitudes are packed into register groups: "greedy" (whole colour classes, each group grown by
 # the class that shares the most currents with it) or "classes" (first-seen class order, cut anywhere).
@@ -336,14 +342,56 @@ class _Group:
         self._use(key)
         return self.name(key)
 
-    def amplitude(self, ai, acc, fac):
+    def class_amplitudes(self, members, acc):
+        """The amplitudes (ai, fac) of one colour class, added into acc with their factors; operands
+        are summed first where the emitter's merge plan says so."""
+        for kind, data in self.em.merge_plan(members):
+            if kind == "one":
+                self.amplitude(data[0], acc, data[1])
+            else:
+                self.merged_amplitude(data[0], data[1], acc)
+
+    def merged_amplitude(self, p, grp, acc):
+        """One closing vertex for the diagrams grp = [(ai, fac), ...], which differ only in the
+        operand at position p (same external legs): fac_0 V(..., sum_i (fac_i / fac_0) X_i, ...)."""
+        em = self.em
+        nd = em.dag.nodes
+        a0, f0 = grp[0]
+        x0 = em.dag.amps[a0].args[p]
+        kind = nd[x0].kind
+        typ, tag = ("vec4<R>", "V") if kind == "V" else ("wsp<R>", "W")
+        cur_key, cur = ("c", x0), self.node(x0)
+        for ai, f in grp[1:]:
+            x = em.dag.amps[ai].args[p]
+            xn = self.node(x)
+            r = Fraction(f) / Fraction(f0)
+            if r == 1:
+                expr = f"{cur} + {xn}"
+                self.flops += FLOPS["sum_" + tag]
+            elif r == -1:
+                expr = f"{cur} - {xn}"
+                self.flops += FLOPS["sum_" + tag]
+            else:
+                expr = f"lin<R>({cur}, R({_lit(r)}), {xn})"
+                self.flops += FLOPS["lin_" + tag]
+            key = ("s", a0, ai)
+            self.lines.append(f"  const {typ} {self.name(key)} = {expr};")
+            self._def(key, SIZES[self.prec][kind])
+            self._use(cur_key)
+            self._use(("c", x))
+            cur_key, cur = key, self.name(key)
+        self.amplitude(a0, acc, f0, override=(p, cur, cur_key))
+
+    def amplitude(self, ai, acc, fac, override=None):
         em = self.em
         amp = em.dag.amps[ai]
         root = em.proc.root
         nd = em.dag.nodes
-        args = [self.node(a) for a in amp.args]
+        args = [override[1] if override and q == override[0] else self.node(a) for q, a in enumerate(amp.args)]
+        if override:
+            self._use(override[2])
         if amp.op in ("vvvx", "ggggx", "iovx"):
-            self._closed_amplitude(ai, amp, args, acc, fac)
+            self._closed_amplitude(ai, amp, args, acc, fac, override)
             return
         r = self.node(em.dag.ext[root])
         if amp.op == "vvv":
@@ -360,12 +408,12 @@ class _Group:
         key = ("a", ai)
         self.lines.append(f"  const cx<R> {self.name(key)} = {expr};")
         self._def(key, SIZES[self.prec]["amp"])
-        for a in amp.args:
-            self._use(("c", a))
+        for q, a in enumerate(amp.args):
+            self._use(override[2] if override and q == override[0] else ("c", a))
         self._use(("c", em.dag.ext[root]))
         self._accumulate(acc, fac, key)
 
-    def _closed_amplitude(self, ai, amp, args, acc, fac):
+    def _closed_amplitude(self, ai, amp, args, acc, fac, override=None):
         """An amplitude contracted at a vertex next to the root (Dag._reclose): every argument is an
         explicit current, the root's among them."""
         nd = self.em.dag.nodes
@@ -381,8 +429,8 @@ class _Group:
         key = ("a", ai)
         self.lines.append(f"  const cx<R> {self.name(key)} = {expr};")
         self._def(key, SIZES[self.prec]["amp"])
-        for a in amp.args:
-            self._use(("c", a))
+        for q, a in enumerate(amp.args):
+            self._use(override[2] if override and q == override[0] else ("c", a))
         self._accumulate(acc, fac, key)
 
     def _accumulate(self, acc, fac, key):
@@ -426,7 +474,37 @@ class Emitter:
         self.cblock = min(divs, key=lambda b: (round(self._block_owners(b, most)[1], 3), -b))
         self.flops = {"double": 0, "float": 0}
         self.algo_flops = 0
+        self._merge_cache = {}
         self.stats = {}
+
+    def merge_plan(self, members):
+        """Closing vertices of one colour class's amplitudes [(ai, fac), ...]: ("merge", (p, grp))
+        for diagrams grp that differ only in their operand at position p, all of one mask (so one
+        momentum), contracted once with the summed operands; ("one", (ai, fac)) for the rest.
+        Greedy, largest group first; deterministic."""
+        key0 = tuple(members)
+        if key0 in self._merge_cache:
+            return self._merge_cache[key0]
+        nd, amps = self.dag.nodes, self.dag.amps
+        left = dict(members)
+        plan = []
+        while MERGE_OPERANDS and len(left) > 1:
+            groups = {}
+            for ai in left:
+                a = amps[ai]
+                for p, x in enumerate(a.args):
+                    k = (a.op, a.piece, p, nd[x].mask, nd[x].kind, a.args[:p] + a.args[p + 1:])
+                    groups.setdefault(k, []).append(ai)
+            k, grp = max(groups.items(), key=lambda kv: (len(kv[1]), -min(kv[1])))
+            if len(grp) < 2:
+                break
+            assert len({amps[ai].args[k[2]] for ai in grp}) == len(grp)
+            plan.append(("merge", (k[2], [(ai, left[ai]) for ai in grp])))
+            for ai in grp:
+                del left[ai]
+        plan.extend(("one", (ai, fac)) for ai, fac in left.items())
+        self._merge_cache[key0] = plan
+        return plan
 
     def _block_owners(self, bsz: int, nwave: int):
         """Longest-first assignment of the colour-sum row blocks (block j spans K' - bsz j columns of
@@ -578,8 +656,7 @@ class Emitter:
             cand = pos
             while cand is not None:
                 items = [(cand, ai, fac) for ai, fac in classes[cand][1]]
-                for it in items:
-                    g.amplitude(it[1], "acc", it[2])
+                g.class_amplitudes(list(classes[cand][1]), "acc")
                 if cur and g.peak() > budget:
                     break
                 cur.extend(items)
@@ -597,8 +674,14 @@ class Emitter:
 
     def _build(self, pat, prec, items, gid):
         g = _Group(self, pat, prec, gid)
+        runs = []                       # consecutive items of one class
         for ci, ai, fac in items:
-            g.amplitude(ai, f"k{ci}", fac)
+            if runs and runs[-1][0] == ci:
+                runs[-1][1].append((ai, fac))
+            else:
+                runs.append((ci, [(ai, fac)]))
+        for ci, members in runs:
+            g.class_amplitudes(members, f"k{ci}")
         return g
 
     # ------------------------------------------------------------------ code
@@ -719,7 +802,8 @@ class Emitter:
         return out
 
     def _algorithmic_flops(self, pat, classes) -> int:
-        """Arithmetic of one configuration with every shared current built once."""
+        """Arithmetic of one configuration with every shared current built once and every closing
+        vertex of the merge plan evaluated once."""
         nd = self.dag.nodes
         used, masks = set(), set()
 
@@ -738,7 +822,17 @@ class Emitter:
                 f += FLOPS[nd[i].op]
                 masks.add(nd[i].mask)
         f += len(masks) * (FLOPS["psum"] + FLOPS["inv"])
-        f += sum(FLOPS[self.dag.amps[ai].op] + FLOPS["class_add"] for ai in pat.amps)
+        for _, members in classes:
+            for kind, data in self.merge_plan(members):
+                if kind == "one":
+                    f += FLOPS[self.dag.amps[data[0]].op] + FLOPS["class_add"]
+                else:
+                    p, grp = data
+                    a0 = self.dag.amps[grp[0][0]]
+                    tag = "V" if nd[a0.args[p]].kind == "V" else "W"
+                    f += FLOPS[a0.op] + FLOPS["class_add"]
+                    f += sum(FLOPS[("sum_" if abs(Fraction(fac) / Fraction(grp[0][1])) == 1 else "lin_") + tag]
+                             for _, fac in grp[1:])
         f += sum(len(vec) * FLOPS["jamp_add"] for vec, _ in classes)
         f += 2 * self.kdim * (self.kdim + 1)
         return f

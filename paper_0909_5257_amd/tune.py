@@ -35,6 +35,10 @@ CANDIDATES = {
     "keep160": {"double": {"budget": 160}, "float": {"budget": 160}},
     "keep200": {"double": {"budget": 192}, "float": {"budget": 200}},
     "keep224": {"double": {"budget": 224}, "float": {"budget": 224}},
+    "keep256": {"double": {"budget": 256}, "float": {"budget": 192}},
+    # large float64 groups (the inlined helicity loop leaves the float64 kernels the whole register
+    # file), small float32 ones (the float32 kernels spill at two waves per SIMD)
+    "keep288": {"double": {"budget": 288}, "float": {"budget": 144}},
     # the same with one call of the wave's work per helicity configuration instead of the loop inlined
     # into the kernel (fewer registers spilled inside the loop where the inlined body spills)
     "keep224c": {"double": {"budget": 224, "calls": True}, "float": {"budget": 224, "calls": True}},

@@ -7,6 +7,8 @@ device routines (the formulas of paper_0909_5257_amd/csrc/heget_device.hpp: pola
 vectors, two-component spinors, the three- and four-gluon and quark-gluon vertices and currents)
 on seeded events and helicity configurations, and requires equality to rounding.  It checks the
 rewrite only: the routines themselves are checked against the oracle by the GPU parity tests.
+The same transcription checks the emitter's merged closing vertices (one contraction with summed
+operands for the diagrams of a colour class that differ in one operand).
 """
 import numpy as np
 import pytest
@@ -49,7 +51,24 @@ def _gggg(a, b, c, d):
     return _mdot(a, d) * _mdot(b, c) - _mdot(a, c) * _mdot(b, d)
 
 
-def _amplitudes(dag, pmom, lam, hq):
+def _closing(dag, amp, a, pm, w, pw, hq):
+    """The closing vertex of one diagram for operand values a with momenta pm (root value w, pw)."""
+    h = hq.get(dag.nodes[amp.args[0]].end)
+    if amp.op == "vvv":
+        return _vvv(a[0], pm[0], a[1], pm[1], w, pw)
+    if amp.op == "gggg":
+        x, y, z = a
+        return _gggg(*[(x, y, z, w), (x, z, w, y), (x, w, y, z)][amp.piece])
+    if amp.op == "iov":
+        return w @ (_smat(a[1], h) @ a[0])
+    if amp.op == "vvvx":
+        return _vvv(a[0], pm[0], a[1], pm[1], a[2], pm[2])
+    if amp.op == "ggggx":
+        return _gggg(*a)
+    return a[1] @ (_smat(a[2], h) @ a[0])
+
+
+def _amplitudes(dag, pmom, lam, hq, with_values=False):
     proc, nd = dag.proc, dag.nodes
 
     def mom(mask):
@@ -86,22 +105,9 @@ def _amplitudes(dag, pmom, lam, hq):
     w, pw = val[dag.ext[root]], mom(1 << root)
     out = []
     for amp in dag.amps:
-        a = [val[x] for x in amp.args]
-        pm = [mom(nd[x].mask) for x in amp.args]
-        h = hq.get(nd[amp.args[0]].end)
-        if amp.op == "vvv":
-            out.append(_vvv(a[0], pm[0], a[1], pm[1], w, pw))
-        elif amp.op == "gggg":
-            x, y, z = a
-            out.append(_gggg(*[(x, y, z, w), (x, z, w, y), (x, w, y, z)][amp.piece]))
-        elif amp.op == "iov":
-            out.append(w @ (_smat(a[1], h) @ a[0]))
-        elif amp.op == "vvvx":
-            out.append(_vvv(a[0], pm[0], a[1], pm[1], a[2], pm[2]))
-        elif amp.op == "ggggx":
-            out.append(_gggg(*a))
-        else:
-            out.append(a[1] @ (_smat(a[2], h) @ a[0]))
+        out.append(_closing(dag, amp, [val[x] for x in amp.args], [mom(nd[x].mask) for x in amp.args], w, pw, hq))
+    if with_values:
+        return np.array(out), val, mom
     return np.array(out)
 
 
@@ -129,3 +135,49 @@ def test_reclosed_amplitudes_equal_root_closed(spec, monkeypatch):
                 a1 = _amplitudes(d1, p, lam, pat.hq)[pat.amps]
                 worst = max(worst, np.abs(a1 - a0).max() / np.abs(a0).max())
     assert worst < 1e-12
+
+
+@pytest.mark.parametrize("spec,any_merge", [("g g > g g g g", True), ("u u~ > g g g g", True),
+                                            ("u u > u u g g", False), ("u g > u g g", False), ("u u~ > u u~", False)])
+def test_merged_closing_vertices_equal_diagram_sums(spec, any_merge):
+    """The emitter's merge plan: within a colour class, diagrams that differ only in one operand of
+    their closing vertex (same external legs, hence the same momentum) are contracted once with the
+    summed operand.  By linearity of every vertex in each operand, fac_0 V(..., sum_i fac_i/fac_0 X_i,
+    ...) equals sum_i fac_i V(..., X_i, ...); the plan covers each amplitude of the class once."""
+    from fractions import Fraction
+    from paper_0909_5257_amd.gen.emit import Emitter, colour_classes
+    from paper_0909_5257_amd.gen.model import Dag, parse
+    dag = Dag(parse(spec))
+    em = Emitter(dag, dag.colour_matrix())
+    nd = dag.nodes
+    ev = generate_events(2, dag.proc.n - 2, KIN_C2, seed=6)
+    worst, merged = 0.0, 0
+    for pat in em.pats:
+        lam = {0: 1, **{g: (1 if j % 2 else -1) for j, g in enumerate(pat.free_gluons)}, **pat.fixed}
+        for q, h in pat.hq.items():
+            lam[q] = h if dag.proc.legs[q].flavour == "u" else -h
+        for p in ev:
+            amps, val, mom = _amplitudes(dag, p, lam, pat.hq, with_values=True)
+            w, pw = val[dag.ext[dag.proc.root]], mom(1 << dag.proc.root)
+            for _, members in colour_classes(em.vectors, pat.amps):
+                plan = em.merge_plan(members)
+                covered = sorted(ai for kind, d in plan for ai in ([d[0]] if kind == "one" else [x for x, _ in d[1]]))
+                assert covered == sorted(ai for ai, _ in members)
+                for kind, d in plan:
+                    if kind == "one":
+                        continue
+                    pos, grp = d
+                    a0, f0 = grp[0]
+                    amp0 = dag.amps[a0]
+                    for ai, _ in grp:
+                        other = dag.amps[ai]
+                        assert other.op == amp0.op and other.piece == amp0.piece
+                        assert all(x == y for q, (x, y) in enumerate(zip(other.args, amp0.args)) if q != pos)
+                        assert nd[other.args[pos]].mask == nd[amp0.args[pos]].mask
+                    direct = sum(float(f) * amps[ai] for ai, f in grp)
+                    xsum = sum(float(Fraction(f) / Fraction(f0)) * val[dag.amps[ai].args[pos]] for ai, f in grp)
+                    a = [xsum if q == pos else val[x] for q, x in enumerate(amp0.args)]
+                    once = float(f0) * _closing(dag, amp0, a, [mom(nd[x].mask) for x in amp0.args], w, pw, pat.hq)
+                    worst = max(worst, abs(once - direct) / max(abs(amps[pat.amps]).max(), 1e-300))
+                    merged += 1
+    assert (merged > 0) == any_merge and worst < 1e-12
