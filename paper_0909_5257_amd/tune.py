@@ -44,6 +44,10 @@ CANDIDATES = {
     "keep224c": {"double": {"budget": 224, "calls": True}, "float": {"budget": 224, "calls": True}},
     # one wave per 64-event group where the colour vector is small enough: no cross-wave
     # accumulation, bit-reproducible results
+    # two float64 waves per SIMD (eight per 64-event workgroup of u u~ > 5g), registers for 256 each
+    "w8k176": {"double": {"budget": 176, "waves_per_cu": 8}, "float": {"externals": "group", "budget": 208}},
+    "w8g192": {"double": {"externals": "group", "budget": 192, "waves_per_cu": 8},
+               "float": {"externals": "group", "budget": 208}},
     "group176s": {"double": {"externals": "group", "budget": 176},
                   "float": {"externals": "group", "budget": 176, "waves_per_cu": 4}},
 }
