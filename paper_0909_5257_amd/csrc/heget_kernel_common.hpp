@@ -109,9 +109,9 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 // generator deals the blocks of the upper triangle to the waves longest first).  The table holds
 // M_ab = W_ab (b > a), W_aa / 2 (b = a), 0 (b < a) in blocks of B rows laid out as [K/B][K][B] so that
 // the B row values of one column are contiguous and wave-uniform (scalar loads).  The column loop is
-// unrolled by 8 so that the loads of eight columns are in flight together.  Result: 2 sum over the
+// unrolled by U so that the loads of U columns are in flight together.  Result: 2 sum over the
 // wave's rows of sum_b M_ab (Re y_a Re y_b + Im y_a Im y_b).
-template <int K, int B>
+template <int K, int B, int U>
 __device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int lane, const int* __restrict__ blocks,
                                                       const double* __restrict__ cmat) {
   static_assert(K % B == 0, "colour block must divide the colour dimension");
@@ -128,7 +128,7 @@ __device__ __forceinline__ double colour_sum_lds_part(double (*yl)[2][64], int l
       tr[a] = 0.0;
       ti[a] = 0.0;
     }
-#pragma unroll 8
+#pragma unroll U
     for (int b = a0; b < K; ++b) {
       const double jr = yl[b][0][lane], ji = yl[b][1][lane];
 #pragma unroll

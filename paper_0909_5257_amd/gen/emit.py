@@ -76,6 +76,9 @@ WAVE_LOOP = True
 # differing operands cover the same external legs (so carry the same momentum), are contracted once
 # with the sum of those operands: the vertex is linear in each operand current.
 MERGE_OPERANDS = True
+REBALANCE_MIN = 0.02      # relative reduction of the largest wave load that a refined assignment must reach
+# Column-loop unroll of the colour sum per precision (measured on u u~ > 5g: 4 for float64, 2 for mixed)
+COLOUR_SUM_UNROLL = {"double": 4, "float": 2}
 GROUP_BUDGET = {"double": 176, "float": 176}   # simulated live 32-bit registers per group
 # How amplitudes are packed into register groups: "greedy" (whole colour classes, each group grown by
 # the class that shares the most currents with it) or "classes" (first-seen class order, cut anywhere).
@@ -762,12 +765,42 @@ class Emitter:
             total_flops += flops + ext_flops
         nwave = self.nwave[prec]
         if nwave > 1:
-            # longest chunk first onto the least loaded wave
+            # longest chunk first onto the least loaded wave, then moves and swaps out of the most
+            # loaded wave while they lower its load (the waves meet at a barrier per configuration);
+            # the refined assignment is kept only where it lowers the largest load by more than
+            # REBALANCE_MIN: a different assignment is different code for the register allocator,
+            # and small gains were measured to be lost to it
             load = [0] * nwave
             for c in sorted(out, key=lambda c: -c[3]):
                 wv = min(range(nwave), key=lambda v: load[v])
                 c[2] = wv
                 load[wv] += c[3]
+            lpt = [c[2] for c in out]
+            lpt_max = max(load)
+            for _ in range(10 * len(out)):
+                top = max(range(nwave), key=lambda v: (load[v], -v))
+                best, gain = None, 0
+                for a in (c for c in out if c[2] == top):
+                    for v in range(nwave):
+                        if v == top:
+                            continue
+                        # move a to v, or swap it with a shorter chunk b of v
+                        for b in [None] + [c for c in out if c[2] == v and c[3] < a[3]]:
+                            d = a[3] - (b[3] if b else 0)
+                            new_max = max(load[top] - d, load[v] + d)
+                            if load[top] - new_max > gain:
+                                best, gain = (a, b, v, d), load[top] - new_max
+                if best is None:
+                    break
+                a, b, v, d = best
+                a[2] = v
+                if b is not None:
+                    b[2] = top
+                load[top] -= d
+                load[v] += d
+            if max(load) > (1.0 - REBALANCE_MIN) * lpt_max:
+                for c, wv in zip(out, lpt):
+                    c[2] = wv
         if MERGE_WAVE_CHUNKS > 1 and total_flops <= MERGE_MAX_PATTERN_FLOPS:
             # a wave's chunks in order, each in a scope of its own after one shared prologue, merged
             # into functions of up to MERGE_WAVE_CHUNKS chunks: fewer calls, fewer saves of
@@ -947,7 +980,7 @@ class Emitter:
                     for nm in names:
                         w(f"      {nm}(cfg, ln);")
                     w("      __syncthreads();")
-                    w(f"      q += colour_sum_lds_part<{self.kdim}, {self.cblock}>(yl, ln, "
+                    w(f"      q += colour_sum_lds_part<{self.kdim}, {self.cblock}, {COLOUR_SUM_UNROLL[prec]}>(yl, ln, "
                       f"&CSB_{'F64' if prec == 'double' else 'F32'}[{v}][0], cmat);")
                     w("      __syncthreads();")
                     w("    }")
@@ -981,7 +1014,7 @@ class Emitter:
                 w("        dst[2 * a + 1] = yl[a][1][lane];")
                 w("      }")
                 w("    }")
-            part = (f"colour_sum_lds_part<{self.kdim}, {self.cblock}>(yl, lane, "
+            part = (f"colour_sum_lds_part<{self.kdim}, {self.cblock}, {COLOUR_SUM_UNROLL[prec]}>(yl, lane, "
                     f"&CSB_{'F64' if prec == 'double' else 'F32'}[wave][0], cmat)")
             if sampled:
                 w(f"    const double part = {part};")

@@ -300,3 +300,24 @@ def test_greedy_plan_covers_every_amplitude_once(spec):
                 for _, ai, fac in g:
                     built.amplitude(ai, "acc", fac)
                 assert built.peak() <= em.budget[prec] or len({ci for ci, _, _ in g}) == 1
+
+
+@pytest.mark.parametrize("spec", ["u u~ > g g g g g", "u u > u u g g g"])
+def test_wave_assignment_never_worse_than_longest_first(spec, monkeypatch):
+    """Cooperative kernels: the chunk-to-wave assignment after the move/swap refinement has a largest
+    wave load no larger than the longest-first assignment's, and it is used only where it gains more
+    than REBALANCE_MIN."""
+    from paper_0909_5257_amd.gen import emit
+    dag = Dag(parse(spec))
+    nmat = dag.colour_matrix()
+    monkeypatch.setattr(emit, "REBALANCE_MIN", 1.0)             # refinement never kept: plain LPT
+    lpt = Emitter(dag, nmat)
+    lpt.emit()
+    monkeypatch.setattr(emit, "REBALANCE_MIN", 0.02)
+    ref = Emitter(dag, nmat)
+    ref.emit()
+    for prec in ("double", "float"):
+        for a, b in zip(lpt.stats[prec], ref.stats[prec]):
+            assert sum(a["wave_flops"]) == sum(b["wave_flops"])
+            assert max(b["wave_flops"]) <= max(a["wave_flops"])
+            assert b["wave_flops"] == a["wave_flops"] or max(b["wave_flops"]) < 0.98 * max(a["wave_flops"])
