@@ -36,10 +36,10 @@ WORKLOAD = [("u u~ > g g g g g", 1 << 20, 0), ("g g > g g g g", 1 << 21, 1)]
 # at the benchmark's full batch sizes (profiles/me2_uux5g_2e20_gg4g_2e21_counters.md).  Keyed by a
 # digest of the kernel's generated source: a kernel that has changed since reports null.
 MEASURED_TRAFFIC = {    # (process, precision): (source digest, HBM bytes per event)
-    ("u u~ > g g g g g", "fp64"): ("704b01b095202863", 23051),
-    ("g g > g g g g", "fp64"): ("cac1defb76d28c7b", 3052),
-    ("u u~ > g g g g g", "mixed"): ("f4f29021da81bd0e", 534),
-    ("g g > g g g g", "mixed"): ("d298c44065b71860", 7759),
+    ("u u~ > g g g g g", "fp64"): ("3cfe84bfda194606", 957),
+    ("g g > g g g g", "fp64"): ("cac1defb76d28c7b", 2013),
+    ("u u~ > g g g g g", "mixed"): ("7df30cd714bdab51", 542),
+    ("g g > g g g g", "mixed"): ("d298c44065b71860", 7677),
 }
 
 

@@ -44,6 +44,11 @@ CANDIDATES = {
     "keep224c": {"double": {"budget": 224, "calls": True}, "float": {"budget": 224, "calls": True}},
     # one wave per 64-event group where the colour vector is small enough: no cross-wave
     # accumulation, bit-reproducible results
+    # float64 budgets around the kept-externals optimum of u u~ > 5g (float: its group-local 208)
+    "keep240": {"double": {"budget": 240}, "float": {"externals": "group", "budget": 208}},
+    "keep264": {"double": {"budget": 264}, "float": {"externals": "group", "budget": 208}},
+    "keep272": {"double": {"budget": 272}, "float": {"externals": "group", "budget": 208}},
+    "keep280": {"double": {"budget": 280}, "float": {"externals": "group", "budget": 208}},
     # two float64 waves per SIMD (eight per 64-event workgroup of u u~ > 5g), registers for 256 each
     "w8k176": {"double": {"budget": 176, "waves_per_cu": 8}, "float": {"externals": "group", "budget": 208}},
     "w8g192": {"double": {"externals": "group", "budget": 192, "waves_per_cu": 8},
