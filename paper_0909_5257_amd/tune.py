@@ -49,6 +49,10 @@ CANDIDATES = {
     "keep264": {"double": {"budget": 264}, "float": {"externals": "group", "budget": 208}},
     "keep272": {"double": {"budget": 272}, "float": {"externals": "group", "budget": 208}},
     "keep280": {"double": {"budget": 280}, "float": {"externals": "group", "budget": 208}},
+    # group-local float32 budgets around 208, with float64 kept-externals budgets around 256
+    "g192": {"double": {"budget": 240}, "float": {"externals": "group", "budget": 192}},
+    "g224": {"double": {"budget": 272}, "float": {"externals": "group", "budget": 224}},
+    "g240": {"double": {"budget": 288}, "float": {"externals": "group", "budget": 240}},
     # two float64 waves per SIMD (eight per 64-event workgroup of u u~ > 5g), registers for 256 each
     "w8k176": {"double": {"budget": 176, "waves_per_cu": 8}, "float": {"externals": "group", "budget": 208}},
     "w8g192": {"double": {"externals": "group", "budget": 192, "waves_per_cu": 8},
